@@ -1,0 +1,184 @@
+/*
+ * mevp.h -- C ABI of the MI355X (gfx950) mEVP momentum-subcycle library.
+ *
+ * The library advances the sea-ice momentum equation of the neXtSIM-DG
+ * dynamical core (Jendersie, Lessig, Richter, "Towards a GPU-Parallelization
+ * of the neXtSIM-DG Dynamical Core", PASC 2024) by mEVP pseudo-time
+ * subcycles: Sec. 2, Eq. (si:momentum) and Eq. (si:mevp); Table 1 names the
+ * four phases of one subcycle (strain, stress, divergence, velocity); the
+ * stress phase is the one printed in Listing 1 and in the appendix listing.
+ * Discretisation (Sec. 2.1): structured quadrilateral mesh, biquadratic
+ * continuous (CG2) velocity, discontinuous (DG) stress with n_s local dofs
+ * per component, DG ice height H and concentration A with n_a dofs.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers. Every array argument is a caller-owned DEVICE pointer (host
+ * pointers are accepted by the copy-in/out calls, which then block the
+ * host). The library never allocates device memory: all of its state lives
+ * in the workspace the caller passes to mevp_create.
+ * Errors. Every call returns a mevp_status; no call aborts or throws. All
+ * argument validation happens on the host before anything is enqueued.
+ * Asynchronous HIP failures surface at the next mevp_sync / mevp_check_*.
+ * Streams. A context enqueues all its work on the stream given at creation
+ * (NULL = the default stream). Calls on one context are stream-ordered;
+ * a context is not thread-safe. Contexts on one device are independent.
+ * Precision. MEVP_FP64 computes everything in IEEE double. MEVP_MIXED stores
+ * the DG stress in float and runs the strain, stress and divergence
+ * contractions in float, keeping the ice-strength exponential, the Delta
+ * denominator, the nodal sums and the velocity update in double. The API
+ * takes and returns double in both modes.
+ * Layouts (C order, element index e = ey*nx + ex, CG2 node index
+ * j = iy*(2nx+1) + ix, vertex index iy*(nx+1) + ix):
+ *   vertex_xy  [2][(nx+1)(ny+1)]     metres, planar coordinates
+ *   H, A       [n_a][nx*ny]          DG coefficients (scaled Legendre basis)
+ *   wind_xy, ocean_xy, v_xy [2][(2nx+1)(2ny+1)]   m/s
+ *   S          [3][n_s][nx*ny]       components 11, 12, 22 of the DG stress
+ * DG basis on the reference square [0,1]^2 with s = xi-1/2, t = eta-1/2:
+ *   1, s, t, s^2-1/12, s t, t^2-1/12, (s^2-1/12) t, s (t^2-1/12)
+ * (the first n_s, resp. n_a, of them). CG2 local node a = 3 b + c sits at
+ * (c/2, b/2) of the reference square.
+ */
+#ifndef MEVP_H
+#define MEVP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MEVP_OK = 0,
+  MEVP_EINVAL = -1,       /* bad argument: null pointer, size, domain index, alignment, parameter */
+  MEVP_ENOMEM = -2,       /* workspace smaller than mevp_workspace_size reports */
+  MEVP_EDEVICE = -3,      /* HIP error: no device, launch failure, asynchronous fault */
+  MEVP_ESTATE = -4,       /* call out of order, e.g. a step before geometry/fields/forcing are set */
+  MEVP_ENONFINITE = -5,   /* non-finite or invalid values found by a check call */
+  MEVP_EUNSUPPORTED = -6  /* the current device is not gfx950 */
+} mevp_status;
+
+typedef enum {
+  MEVP_FP64 = 0,
+  MEVP_MIXED = 1
+} mevp_precision;
+
+/* Physical and iteration parameters (mevp_default_params fills the values
+ * the paper uses: P* and the factor 20 of the stress listings, 100 subcycles
+ * per 120 s step of Sec. 4, alpha = beta = 300; the rest are conventional
+ * viscous-plastic constants the paper does not state). */
+typedef struct {
+  double Pstar;    /* ice strength P* [N m^-2] */
+  double C;        /* concentration exponent factor (20 in the listings) */
+  double DeltaMin; /* Delta_min [s^-1], regularises the viscosities */
+  double alpha;    /* mEVP stress relaxation, > 0 */
+  double beta;     /* mEVP velocity relaxation, >= 0 */
+  double rho_i;    /* ice density [kg m^-3] */
+  double rho_a;    /* air density */
+  double C_a;      /* air drag coefficient */
+  double rho_o;    /* ocean density */
+  double C_o;      /* ocean drag coefficient */
+  double f_cor;    /* Coriolis parameter [s^-1] */
+  double dt;       /* time step of one mevp_step [s], > 0 */
+  int relax_form;  /* 0: S <- (1-1/alpha) S + (1/alpha) M^-1(...) as in both listings;
+                      1: alpha/(1+alpha) and 1/(1+alpha) as in Eq. (si:mevp) */
+} mevp_params;
+
+/* One independent domain: nx x ny elements, n_s in {3, 6, 8} stress dofs
+ * (Gauss rule 2x2 for n_s = 3, 3x3 otherwise, as in the appendix listing),
+ * n_a in {1, 3, 6} dofs for H and A. All domains of one context must share
+ * n_s and n_a. */
+typedef struct {
+  int nx, ny, n_s, n_a;
+} mevp_domain_desc;
+
+typedef struct mevp_ctx mevp_ctx;
+
+/* Fill *out with the default parameters. EINVAL if out is NULL. */
+mevp_status mevp_default_params(mevp_params *out);
+
+/* Bytes of device workspace a context for these domains needs (Sec. 3.2: the
+ * per-element inverse mass maps are recomputed from the four vertices of each
+ * cell, so the workspace holds fields and state only). EINVAL on bad
+ * descriptors, n_domains < 1, mixed n_s / n_a, or more than 2^31-1 elements
+ * or nodes in total. */
+mevp_status mevp_workspace_size(const mevp_domain_desc *domains, int n_domains,
+                                mevp_precision precision, size_t *bytes);
+
+/* Create a context. `workspace` is a caller-owned device buffer of at least
+ * mevp_workspace_size bytes, 256-byte aligned, that must outlive the context.
+ * `hip_stream` is a hipStream_t (NULL = default stream). Checks that the
+ * current device is gfx950 (EUNSUPPORTED otherwise). Enqueues the zeroing of
+ * the state (v = 0, S = 0) on the stream. On success *out owns host memory
+ * released by mevp_destroy. */
+mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
+                        const mevp_domain_desc *domains, int n_domains, void *workspace,
+                        size_t ws_bytes, void *hip_stream, mevp_ctx **out);
+
+/* Replace the parameters (validated as in mevp_create). */
+mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params);
+
+/* Copy-in calls (stream-ordered; the caller may reuse its buffer once the
+ * stream has passed the call). Layouts as above. */
+mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy);
+mevp_status mevp_set_fields(mevp_ctx *ctx, int dom, const double *H, const double *A);
+mevp_status mevp_set_forcing(mevp_ctx *ctx, int dom, const double *wind_xy,
+                             const double *ocean_xy);
+/* State (v, S) of domain `dom`. In MEVP_MIXED, S is rounded to float. */
+mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const double *S);
+
+/* One time step of every domain (Sec. 2: momentum and mEVP subcycled inside
+ * one advection step): mevp_begin_step, then mevp_subcycles(n_subcycles).
+ * ESTATE unless geometry, fields and forcing of every domain were set. */
+mevp_status mevp_step(mevp_ctx *ctx, int n_subcycles);
+
+/* Start a time step: v^n <- v, and per node the lumped ice mass
+ * M^H = int rho_i h phi, lumped concentration m^A = int a phi (h, a clamped
+ * as in the stress listings) and air stress rho_a C_a |v_a| v_a. */
+mevp_status mevp_begin_step(mevp_ctx *ctx);
+
+/* n >= 0 mEVP subcycles (Eq. (si:mevp)) using the v^n of the last
+ * mevp_begin_step: strain E from v^(p-1); stress update of Listing 1,
+ * S <- fac S + ainv M^-1 Psi W s(E); divergence F_j = sum over the elements
+ * around node j, in ascending element order, of -int sigma grad phi_j;
+ * lumped-mass velocity update with beta relaxation, air drag, lagged ocean
+ * drag and implicit Coriolis; v = 0 on the outer boundary. */
+mevp_status mevp_subcycles(mevp_ctx *ctx, int n);
+
+/* Copy out the state of domain `dom` (either pointer may be NULL). */
+mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S);
+
+/* Wait for the context's stream; EDEVICE if any enqueued work failed. */
+mevp_status mevp_sync(mevp_ctx *ctx);
+
+/* Synchronous device checks. check_inputs: every vertex, H, A, wind and
+ * ocean value finite and every element Jacobian positive at every Gauss
+ * point; check_state: every v and S value finite. ENONFINITE if not. */
+mevp_status mevp_check_inputs(mevp_ctx *ctx);
+mevp_status mevp_check_state(mevp_ctx *ctx);
+
+/* Kernel timing for measurement (the paper times kernels alone, with
+ * barriers around them, Sec. 4). enable: record a HIP event pair around each
+ * of the next `max_launches` launches of every phase on the context's stream
+ * (0 disables and frees the events). read: wait for the stream, then return
+ * per phase (0 = element phase, 1 = node phase, 2 = start of step) the number
+ * of timed launches and their summed duration in milliseconds, and restart
+ * the count. Arrays have 3 entries; either may be NULL. */
+mevp_status mevp_timing_enable(mevp_ctx *ctx, int max_launches);
+mevp_status mevp_timing_read(mevp_ctx *ctx, int *count, double *total_ms);
+
+/* Release the context's host memory (the workspace stays the caller's).
+ * Does not synchronise. NULL is a no-op. */
+void mevp_destroy(mevp_ctx *ctx);
+
+/* Static description of a status code. */
+const char *mevp_status_string(mevp_status s);
+
+/* Library version string. */
+const char *mevp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEVP_H */

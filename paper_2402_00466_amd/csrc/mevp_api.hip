@@ -1,0 +1,531 @@
+// mevp_api.hip -- host runtime behind the C ABI of include/mevp.h.
+//
+// Holds no numerics: validates arguments on the host, carves the caller's
+// device workspace into the context's arrays, builds the block -> (domain,
+// first element/node) maps for batched launches, and enqueues the kernels of
+// mevp_kernels.hip on the context's stream.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "mevp.h"
+#include "mevp_internal.hpp"
+
+using namespace mevp;
+
+struct mevp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  mevp_precision prec = MEVP_FP64;
+  mevp_params params{};
+  KParams kp{};
+  int nd = 0, ns = 0, na = 0;
+  std::vector<mevp_domain_desc> desc;
+  std::vector<DomDev> dom_h;
+  std::vector<Blk> eblk_h, nblk_h;
+  DevArrays d{};
+  DomDev *doms_d = nullptr;
+  Blk *eblk_d = nullptr, *nblk_d = nullptr;
+  size_t tot_e = 0, tot_n = 0, tot_v = 0;
+  std::vector<unsigned char> geo_set, fld_set, frc_set;
+  // optional kernel timing: event pairs per phase
+  struct Timer {
+    std::vector<hipEvent_t> ev;  // 2 per launch
+    int used = 0;
+  } timer[3];
+  int timer_cap = 0;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr long long kIndexMax = 0x7fffffffLL;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool finite(double x) { return isfinite(x) != 0; }
+
+mevp_status validate_params(const mevp_params *p) {
+  if (!p) return MEVP_EINVAL;
+  const double v[] = {p->Pstar, p->C, p->DeltaMin, p->alpha, p->beta, p->rho_i, p->rho_a,
+                      p->C_a, p->rho_o, p->C_o, p->f_cor, p->dt};
+  for (double x : v)
+    if (!finite(x)) return MEVP_EINVAL;
+  if (p->Pstar < 0 || p->DeltaMin <= 0 || p->alpha <= 0 || p->beta < 0 || p->dt <= 0 ||
+      p->rho_i <= 0 || p->rho_a < 0 || p->C_a < 0 || p->rho_o < 0 || p->C_o < 0)
+    return MEVP_EINVAL;
+  if (p->relax_form != 0 && p->relax_form != 1) return MEVP_EINVAL;
+  return MEVP_OK;
+}
+
+KParams derive(const mevp_params &p) {
+  KParams k{};
+  k.Pstar = p.Pstar;
+  k.C = p.C;
+  k.dmin2 = p.DeltaMin * p.DeltaMin;
+  if (p.relax_form == 1) {
+    k.fac = p.alpha / (1.0 + p.alpha);
+    k.ainv = 1.0 / (1.0 + p.alpha);
+  } else {
+    k.ainv = 1.0 / p.alpha;
+    k.fac = 1.0 - k.ainv;
+  }
+  k.beta = p.beta;
+  k.inv_dt = 1.0 / p.dt;
+  k.rho_i = p.rho_i;
+  k.rhoCa = p.rho_a * p.C_a;
+  k.rhoCo = p.rho_o * p.C_o;
+  k.f_cor = p.f_cor;
+  return k;
+}
+
+// Layout of the workspace: offsets in bytes of every array.
+struct Layout {
+  size_t doms, eblk, nblk, flag, vert, H, A, wind, ocean, v, vn, tau, MH, mA, S, fe, total;
+  size_t tot_e, tot_n, tot_v;
+  int n_eblk, n_nblk;
+  int ns, na;
+};
+
+mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout *L) {
+  if (!dd || nd < 1) return MEVP_EINVAL;
+  if (prec != MEVP_FP64 && prec != MEVP_MIXED) return MEVP_EINVAL;
+  const int ns = dd[0].n_s, na = dd[0].n_a;
+  if (!(ns == 3 || ns == 6 || ns == 8) || !(na == 1 || na == 3 || na == 6)) return MEVP_EINVAL;
+  long long te = 0, tn = 0, tv = 0, neb = 0, nnb = 0;
+  for (int i = 0; i < nd; ++i) {
+    const mevp_domain_desc &d = dd[i];
+    if (d.n_s != ns || d.n_a != na) return MEVP_EINVAL;
+    if (d.nx < 1 || d.ny < 1 || d.nx > 1000000 || d.ny > 1000000) return MEVP_EINVAL;
+    const long long e = (long long)d.nx * d.ny;
+    const long long n = (2LL * d.nx + 1) * (2LL * d.ny + 1);
+    const long long v = ((long long)d.nx + 1) * (d.ny + 1);
+    te += e;
+    tn += n;
+    tv += v;
+    neb += (e + kElemBlock - 1) / kElemBlock;
+    nnb += (n + kNodeBlock - 1) / kNodeBlock;
+    if (te > kIndexMax || tn > kIndexMax || 2 * tn > kIndexMax || 18 * te > (1LL << 40))
+      return MEVP_EINVAL;
+  }
+  const size_t ws = (prec == MEVP_MIXED) ? sizeof(float) : sizeof(double);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L->doms = take(sizeof(DomDev) * nd);
+  L->eblk = take(sizeof(Blk) * neb);
+  L->nblk = take(sizeof(Blk) * nnb);
+  L->flag = take(sizeof(int) * 4);
+  L->vert = take(sizeof(double) * 2 * tv);
+  L->H = take(sizeof(double) * na * te);
+  L->A = take(sizeof(double) * na * te);
+  L->wind = take(sizeof(double) * 2 * tn);
+  L->ocean = take(sizeof(double) * 2 * tn);
+  L->v = take(sizeof(double) * 2 * tn);
+  L->vn = take(sizeof(double) * 2 * tn);
+  L->tau = take(sizeof(double) * 2 * tn);
+  L->MH = take(sizeof(double) * tn);
+  L->mA = take(sizeof(double) * tn);
+  L->S = take(ws * 3 * ns * te);
+  L->fe = take(ws * 18 * te);
+  L->total = off;
+  L->tot_e = (size_t)te;
+  L->tot_n = (size_t)tn;
+  L->tot_v = (size_t)tv;
+  L->n_eblk = (int)neb;
+  L->n_nblk = (int)nnb;
+  L->ns = ns;
+  L->na = na;
+  return MEVP_OK;
+}
+
+mevp_status hip_status(hipError_t e) { return e == hipSuccess ? MEVP_OK : MEVP_EDEVICE; }
+
+bool bad_dom(const mevp_ctx *c, int dom) { return !c || dom < 0 || dom >= c->nd; }
+
+// copy with either host or device source/destination, stream-ordered
+mevp_status copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return MEVP_OK;
+  return hip_status(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s));
+}
+
+void timer_free(mevp_ctx *c) {
+  for (auto &t : c->timer) {
+    for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+    t.ev.clear();
+    t.used = 0;
+  }
+  c->timer_cap = 0;
+}
+
+// Record the start event of phase `ph` if timing is on and slots remain;
+// returns the slot or -1.
+int timer_start(mevp_ctx *c, int ph) {
+  auto &t = c->timer[ph];
+  if (c->timer_cap == 0 || t.used >= c->timer_cap) return -1;
+  if (hipEventRecord(t.ev[2 * t.used], c->stream) != hipSuccess) return -1;
+  return t.used;
+}
+void timer_stop(mevp_ctx *c, int ph, int slot) {
+  if (slot < 0) return;
+  auto &t = c->timer[ph];
+  if (hipEventRecord(t.ev[2 * slot + 1], c->stream) == hipSuccess) t.used = slot + 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mevp_version(void) { return "mevp-gfx950 0.1.0"; }
+
+const char *mevp_status_string(mevp_status s) {
+  switch (s) {
+    case MEVP_OK: return "ok";
+    case MEVP_EINVAL: return "invalid argument";
+    case MEVP_ENOMEM: return "workspace too small";
+    case MEVP_EDEVICE: return "device error";
+    case MEVP_ESTATE: return "call out of order";
+    case MEVP_ENONFINITE: return "non-finite or invalid values";
+    case MEVP_EUNSUPPORTED: return "unsupported device";
+  }
+  return "unknown status";
+}
+
+mevp_status mevp_default_params(mevp_params *out) {
+  if (!out) return MEVP_EINVAL;
+  out->Pstar = 27500.0;
+  out->C = 20.0;
+  out->DeltaMin = 2e-9;
+  out->alpha = 300.0;
+  out->beta = 300.0;
+  out->rho_i = 900.0;
+  out->rho_a = 1.3;
+  out->C_a = 1.2e-3;
+  out->rho_o = 1026.0;
+  out->C_o = 5.5e-3;
+  out->f_cor = 1.46e-4;
+  out->dt = 120.0;
+  out->relax_form = 0;
+  return MEVP_OK;
+}
+
+mevp_status mevp_workspace_size(const mevp_domain_desc *domains, int n_domains,
+                                mevp_precision precision, size_t *bytes) {
+  if (!bytes) return MEVP_EINVAL;
+  Layout L;
+  mevp_status st = plan(domains, n_domains, precision, &L);
+  if (st != MEVP_OK) return st;
+  *bytes = L.total;
+  return MEVP_OK;
+}
+
+mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
+                        const mevp_domain_desc *domains, int n_domains, void *workspace,
+                        size_t ws_bytes, void *hip_stream, mevp_ctx **out) {
+  if (!out) return MEVP_EINVAL;
+  *out = nullptr;
+  mevp_status st = validate_params(params);
+  if (st != MEVP_OK) return st;
+  Layout L;
+  st = plan(domains, n_domains, precision, &L);
+  if (st != MEVP_OK) return st;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return MEVP_EINVAL;
+  if (ws_bytes < L.total) return MEVP_ENOMEM;
+
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MEVP_EDEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MEVP_EDEVICE;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MEVP_EUNSUPPORTED;
+
+  mevp_ctx *c = new (std::nothrow) mevp_ctx();
+  if (!c) return MEVP_EINVAL;
+  c->device = dev;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->prec = precision;
+  c->params = *params;
+  c->kp = derive(*params);
+  c->nd = n_domains;
+  c->ns = L.ns;
+  c->na = L.na;
+  c->desc.assign(domains, domains + n_domains);
+  c->tot_e = L.tot_e;
+  c->tot_n = L.tot_n;
+  c->tot_v = L.tot_v;
+  c->geo_set.assign(n_domains, 0);
+  c->fld_set.assign(n_domains, 0);
+  c->frc_set.assign(n_domains, 0);
+
+  int eo = 0, no = 0, vo = 0;
+  for (int i = 0; i < n_domains; ++i) {
+    const mevp_domain_desc &dd = domains[i];
+    DomDev D;
+    D.nx = dd.nx;
+    D.ny = dd.ny;
+    D.ne = dd.nx * dd.ny;
+    D.nn = (2 * dd.nx + 1) * (2 * dd.ny + 1);
+    D.nv = (dd.nx + 1) * (dd.ny + 1);
+    D.elem_off = eo;
+    D.node_off = no;
+    D.vert_off = vo;
+    eo += D.ne;
+    no += D.nn;
+    vo += D.nv;
+    c->dom_h.push_back(D);
+    for (int f = 0; f < D.ne; f += kElemBlock) c->eblk_h.push_back(Blk{i, f});
+    for (int f = 0; f < D.nn; f += kNodeBlock) c->nblk_h.push_back(Blk{i, f});
+  }
+
+  char *base = static_cast<char *>(workspace);
+  c->doms_d = reinterpret_cast<DomDev *>(base + L.doms);
+  c->eblk_d = reinterpret_cast<Blk *>(base + L.eblk);
+  c->nblk_d = reinterpret_cast<Blk *>(base + L.nblk);
+  DevArrays &d = c->d;
+  d.doms = c->doms_d;
+  d.eblk = c->eblk_d;
+  d.nblk = c->nblk_d;
+  d.flag = reinterpret_cast<int *>(base + L.flag);
+  d.vert = reinterpret_cast<double *>(base + L.vert);
+  d.H = reinterpret_cast<double *>(base + L.H);
+  d.A = reinterpret_cast<double *>(base + L.A);
+  d.wind = reinterpret_cast<double *>(base + L.wind);
+  d.ocean = reinterpret_cast<double *>(base + L.ocean);
+  d.v = reinterpret_cast<double *>(base + L.v);
+  d.vn = reinterpret_cast<double *>(base + L.vn);
+  d.tau = reinterpret_cast<double *>(base + L.tau);
+  d.MH = reinterpret_cast<double *>(base + L.MH);
+  d.mA = reinterpret_cast<double *>(base + L.mA);
+  d.S = base + L.S;
+  d.fe = base + L.fe;
+
+  hipStream_t s = c->stream;
+  mevp_status rc = copy(c->doms_d, c->dom_h.data(), sizeof(DomDev) * n_domains, s);
+  if (rc == MEVP_OK) rc = copy(c->eblk_d, c->eblk_h.data(), sizeof(Blk) * c->eblk_h.size(), s);
+  if (rc == MEVP_OK) rc = copy(c->nblk_d, c->nblk_h.data(), sizeof(Blk) * c->nblk_h.size(), s);
+  // zero everything after the tables: fields, state, scratch
+  if (rc == MEVP_OK)
+    rc = hip_status(launch_fill(base + L.flag, (L.total - L.flag) / 4, 0u, s));
+  // the host vectors above must outlive the asynchronous copies
+  if (rc == MEVP_OK) rc = hip_status(hipStreamSynchronize(s));
+  if (rc != MEVP_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return MEVP_OK;
+}
+
+mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params) {
+  if (!ctx) return MEVP_EINVAL;
+  mevp_status st = validate_params(params);
+  if (st != MEVP_OK) return st;
+  ctx->params = *params;
+  ctx->kp = derive(*params);
+  return MEVP_OK;
+}
+
+mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy) {
+  if (bad_dom(ctx, dom) || !vertex_xy) return MEVP_EINVAL;
+  const DomDev &D = ctx->dom_h[dom];
+  mevp_status st = copy(const_cast<double *>(ctx->d.vert) + 2 * (size_t)D.vert_off, vertex_xy,
+                        sizeof(double) * 2 * D.nv, ctx->stream);
+  if (st == MEVP_OK) ctx->geo_set[dom] = 1;
+  return st;
+}
+
+mevp_status mevp_set_fields(mevp_ctx *ctx, int dom, const double *H, const double *A) {
+  if (bad_dom(ctx, dom) || !H || !A) return MEVP_EINVAL;
+  const DomDev &D = ctx->dom_h[dom];
+  const size_t n = (size_t)ctx->na * D.ne;
+  mevp_status st = copy(const_cast<double *>(ctx->d.H) + (size_t)ctx->na * D.elem_off, H,
+                        sizeof(double) * n, ctx->stream);
+  if (st == MEVP_OK)
+    st = copy(const_cast<double *>(ctx->d.A) + (size_t)ctx->na * D.elem_off, A,
+              sizeof(double) * n, ctx->stream);
+  if (st == MEVP_OK) ctx->fld_set[dom] = 1;
+  return st;
+}
+
+mevp_status mevp_set_forcing(mevp_ctx *ctx, int dom, const double *wind_xy,
+                             const double *ocean_xy) {
+  if (bad_dom(ctx, dom) || !wind_xy || !ocean_xy) return MEVP_EINVAL;
+  const DomDev &D = ctx->dom_h[dom];
+  const size_t o = 2 * (size_t)D.node_off, n = 2 * (size_t)D.nn;
+  mevp_status st = copy(const_cast<double *>(ctx->d.wind) + o, wind_xy, sizeof(double) * n,
+                        ctx->stream);
+  if (st == MEVP_OK)
+    st = copy(const_cast<double *>(ctx->d.ocean) + o, ocean_xy, sizeof(double) * n, ctx->stream);
+  if (st == MEVP_OK) ctx->frc_set[dom] = 1;
+  return st;
+}
+
+mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const double *S) {
+  if (bad_dom(ctx, dom) || !v_xy || !S) return MEVP_EINVAL;
+  const DomDev &D = ctx->dom_h[dom];
+  mevp_status st = copy(ctx->d.v + 2 * (size_t)D.node_off, v_xy, sizeof(double) * 2 * D.nn,
+                        ctx->stream);
+  if (st != MEVP_OK) return st;
+  const size_t n = (size_t)3 * ctx->ns * D.ne, o = (size_t)3 * ctx->ns * D.elem_off;
+  if (ctx->prec == MEVP_FP64) return copy(static_cast<double *>(ctx->d.S) + o, S, sizeof(double) * n, ctx->stream);
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, S) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return MEVP_EINVAL;  // the rounding to float runs on the device: S must be device memory
+  }
+  return hip_status(launch_convert_d2f(S, static_cast<float *>(ctx->d.S) + o, n, ctx->stream));
+}
+
+mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S) {
+  if (bad_dom(ctx, dom)) return MEVP_EINVAL;
+  const DomDev &D = ctx->dom_h[dom];
+  if (v_xy) {
+    mevp_status st = copy(v_xy, ctx->d.v + 2 * (size_t)D.node_off, sizeof(double) * 2 * D.nn,
+                          ctx->stream);
+    if (st != MEVP_OK) return st;
+  }
+  if (S) {
+    const size_t n = (size_t)3 * ctx->ns * D.ne, o = (size_t)3 * ctx->ns * D.elem_off;
+    if (ctx->prec == MEVP_FP64) return copy(S, static_cast<double *>(ctx->d.S) + o, sizeof(double) * n, ctx->stream);
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, S) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      return MEVP_EINVAL;
+    }
+    return hip_status(launch_convert_f2d(static_cast<const float *>(ctx->d.S) + o, S, n, ctx->stream));
+  }
+  return MEVP_OK;
+}
+
+mevp_status mevp_begin_step(mevp_ctx *ctx) {
+  if (!ctx) return MEVP_EINVAL;
+  for (int i = 0; i < ctx->nd; ++i)
+    if (!ctx->geo_set[i] || !ctx->fld_set[i] || !ctx->frc_set[i]) return MEVP_ESTATE;
+  const int slot = timer_start(ctx, 2);
+  mevp_status st = hip_status(launch_begin_step(ctx->d, ctx->kp, ctx->na, ctx->ns,
+                                                (int)ctx->nblk_h.size(), ctx->stream));
+  timer_stop(ctx, 2, slot);
+  return st;
+}
+
+mevp_status mevp_subcycles(mevp_ctx *ctx, int n) {
+  if (!ctx || n < 0) return MEVP_EINVAL;
+  for (int i = 0; i < ctx->nd; ++i)
+    if (!ctx->geo_set[i] || !ctx->fld_set[i] || !ctx->frc_set[i]) return MEVP_ESTATE;
+  const bool mixed = ctx->prec == MEVP_MIXED;
+  for (int it = 0; it < n; ++it) {
+    int slot = timer_start(ctx, 0);
+    hipError_t e = launch_element_phase(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed,
+                                        (int)ctx->eblk_h.size(), ctx->stream);
+    timer_stop(ctx, 0, slot);
+    if (e == hipSuccess) {
+      slot = timer_start(ctx, 1);
+      e = launch_node_phase(ctx->d, ctx->kp, mixed, (int)ctx->nblk_h.size(), ctx->stream);
+      timer_stop(ctx, 1, slot);
+    }
+    if (e != hipSuccess) return MEVP_EDEVICE;
+  }
+  return MEVP_OK;
+}
+
+mevp_status mevp_step(mevp_ctx *ctx, int n_subcycles) {
+  if (!ctx || n_subcycles < 0) return MEVP_EINVAL;
+  mevp_status st = mevp_begin_step(ctx);
+  if (st != MEVP_OK) return st;
+  return mevp_subcycles(ctx, n_subcycles);
+}
+
+mevp_status mevp_sync(mevp_ctx *ctx) {
+  if (!ctx) return MEVP_EINVAL;
+  return hip_status(hipStreamSynchronize(ctx->stream));
+}
+
+static mevp_status read_flag(mevp_ctx *ctx, int *flag) {
+  mevp_status st = hip_status(hipMemcpyAsync(flag, ctx->d.flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(ctx->stream));
+  return st;
+}
+
+mevp_status mevp_check_inputs(mevp_ctx *ctx) {
+  if (!ctx) return MEVP_EINVAL;
+  hipStream_t s = ctx->stream;
+  mevp_status st = hip_status(launch_fill(ctx->d.flag, 1, 0u, s));
+  const size_t te = ctx->tot_e, tn = ctx->tot_n;
+  if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.vert, 2 * ctx->tot_v, ctx->d.flag, 1, s));
+  if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.H, ctx->na * te, ctx->d.flag, 1, s));
+  if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.A, ctx->na * te, ctx->d.flag, 1, s));
+  if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.wind, 2 * tn, ctx->d.flag, 1, s));
+  if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.ocean, 2 * tn, ctx->d.flag, 1, s));
+  if (st == MEVP_OK)
+    st = hip_status(launch_check_jacobian(ctx->d, ctx->ns, (int)ctx->eblk_h.size(), 2, s));
+  int flag = 0;
+  if (st == MEVP_OK) st = read_flag(ctx, &flag);
+  if (st != MEVP_OK) return st;
+  return flag ? MEVP_ENONFINITE : MEVP_OK;
+}
+
+mevp_status mevp_check_state(mevp_ctx *ctx) {
+  if (!ctx) return MEVP_EINVAL;
+  hipStream_t s = ctx->stream;
+  mevp_status st = hip_status(launch_fill(ctx->d.flag, 1, 0u, s));
+  const size_t nS = (size_t)3 * ctx->ns * ctx->tot_e;
+  if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.v, 2 * ctx->tot_n, ctx->d.flag, 1, s));
+  if (st == MEVP_OK) {
+    if (ctx->prec == MEVP_FP64)
+      st = hip_status(launch_check_finite(static_cast<const double *>(ctx->d.S), nS, ctx->d.flag, 1, s));
+    else
+      st = hip_status(launch_check_finite_f(static_cast<const float *>(ctx->d.S), nS, ctx->d.flag, 1, s));
+  }
+  int flag = 0;
+  if (st == MEVP_OK) st = read_flag(ctx, &flag);
+  if (st != MEVP_OK) return st;
+  return flag ? MEVP_ENONFINITE : MEVP_OK;
+}
+
+mevp_status mevp_timing_enable(mevp_ctx *ctx, int max_launches) {
+  if (!ctx || max_launches < 0 || max_launches > (1 << 20)) return MEVP_EINVAL;
+  mevp_status st = hip_status(hipStreamSynchronize(ctx->stream));
+  timer_free(ctx);
+  if (st != MEVP_OK || max_launches == 0) return st;
+  for (auto &t : ctx->timer) {
+    t.ev.resize(2 * (size_t)max_launches);
+    for (auto &e : t.ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        timer_free(ctx);
+        return MEVP_EDEVICE;
+      }
+  }
+  ctx->timer_cap = max_launches;
+  return MEVP_OK;
+}
+
+mevp_status mevp_timing_read(mevp_ctx *ctx, int *count, double *total_ms) {
+  if (!ctx) return MEVP_EINVAL;
+  mevp_status st = hip_status(hipStreamSynchronize(ctx->stream));
+  if (st != MEVP_OK) return st;
+  for (int ph = 0; ph < 3; ++ph) {
+    auto &t = ctx->timer[ph];
+    double sum = 0.0;
+    for (int i = 0; i < t.used; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]) != hipSuccess) return MEVP_EDEVICE;
+      sum += ms;
+    }
+    if (count) count[ph] = t.used;
+    if (total_ms) total_ms[ph] = sum;
+    t.used = 0;
+  }
+  return MEVP_OK;
+}
+
+void mevp_destroy(mevp_ctx *ctx) {
+  if (!ctx) return;
+  timer_free(ctx);
+  delete ctx;
+}
+
+}  // extern "C"

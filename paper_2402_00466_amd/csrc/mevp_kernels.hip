@@ -1,0 +1,586 @@
+// mevp_kernels.hip -- gfx950 kernels of the mEVP momentum subcycle.
+//
+// One subcycle (Table 1 of the paper: strain, stress, divergence, velocity)
+// is two launches:
+//   element phase  one element per lane: gather the 9 CG2 velocities, strain
+//                  rates at the Gauss points, L2 projection onto the DG stress
+//                  space, the VP stress update of Listing 1 (S read and
+//                  written once), the new stress at the Gauss points and the
+//                  weak-form nodal forces of the element (18 values, written
+//                  to a scratch array, element-fastest);
+//   node phase     one CG2 node per lane: sum the forces of the <= 4 elements
+//                  around the node in ascending element order (deterministic,
+//                  no atomics), then the lumped-mass velocity update.
+// The per-element mass matrix and its inverse map are recomputed from the four
+// cell vertices in every subcycle (the paper's "on-the-fly map", Sec. 3.2)
+// instead of being stored: 64 B of vertices per element instead of a
+// n_s x n_G matrix.
+//
+// Arrays are element- or node-fastest (structure of arrays), so consecutive
+// lanes touch consecutive addresses for S, H, A, the forces and the node
+// arrays; the 3x3 velocity gather of neighbouring elements overlaps and is
+// served from L2.
+#include "mevp_internal.hpp"
+#include "mevp_ref.hpp"
+
+namespace mevp {
+namespace {
+
+template <class T>
+__device__ __forceinline__ T ld(const void *base, size_t i) {
+  return static_cast<const T *>(base)[i];
+}
+
+// Bilinear cell map from the vertices (0,0), (1,0), (0,1), (1,1) of the
+// reference square: J(xi, eta) = [[J00, J01], [J10, J11]] with
+//   J00 = (1-eta) ax + eta bx, J01 = (1-xi) cx + xi dx, and the same in y.
+template <class T>
+struct Cell {
+  T ax, bx, cx, dx, ay, by, cy, dy;
+  __device__ __forceinline__ void jac(double xi, double eta, T &J00, T &J01, T &J10,
+                                      T &J11) const {
+    J00 = T(1.0 - eta) * ax + T(eta) * bx;
+    J01 = T(1.0 - xi) * cx + T(xi) * dx;
+    J10 = T(1.0 - eta) * ay + T(eta) * by;
+    J11 = T(1.0 - xi) * cy + T(xi) * dy;
+  }
+};
+
+template <class T>
+__device__ __forceinline__ Cell<T> load_cell(const DomDev &D, const double *vert, int ex, int ey) {
+  const double *VX = vert + 2 * (size_t)D.vert_off;
+  const double *VY = VX + D.nv;
+  const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
+  const double X0 = VX[i0], X1 = VX[i0 + 1], X2 = VX[i2], X3 = VX[i2 + 1];
+  const double Y0 = VY[i0], Y1 = VY[i0 + 1], Y2 = VY[i2], Y3 = VY[i2 + 1];
+  Cell<T> c;
+  c.ax = T(X1 - X0);
+  c.bx = T(X3 - X2);
+  c.cx = T(X2 - X0);
+  c.dx = T(X3 - X1);
+  c.ay = T(Y1 - Y0);
+  c.by = T(Y3 - Y2);
+  c.cy = T(Y2 - Y0);
+  c.dy = T(Y3 - Y1);
+  return c;
+}
+
+// Local mass matrix M_e = Psi W_e Psi^T (W_e = diag(w_q |J_q|)) factorised as
+// L D L^T with unit lower L; solve() applies M_e^-1 in place.
+template <int NS, class T>
+struct Ldl {
+  T L[NS][NS];
+  T invd[NS];
+  template <class Q>
+  __device__ __forceinline__ void build(const Cell<T> &c) {
+    T M[NS][NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+      for (int l = 0; l <= k; ++l) M[k][l] = T(0);
+#pragma unroll
+    for (int q = 0; q < Q::NG; ++q) {
+      T J00, J01, J10, J11;
+      c.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+      const T wd = T(Q::w(q)) * (J00 * J11 - J01 * J10);
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int l = 0; l <= k; ++l) {
+          const double pp = Q::psi(k, q) * Q::psi(l, q);
+          if (pp != 0.0) M[k][l] += T(pp) * wd;
+        }
+    }
+    T dv[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      T dj = M[j][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k] * dv[k];
+      dv[j] = dj;
+      invd[j] = T(1) / dj;
+#pragma unroll
+      for (int i = j + 1; i < NS; ++i) {
+        T s = M[i][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k] * dv[k];
+        L[i][j] = s * invd[j];
+      }
+    }
+  }
+  __device__ __forceinline__ void solve(T (&x)[NS]) const {
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+#pragma unroll
+      for (int k = 0; k < i; ++k) x[i] -= L[i][k] * x[k];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] *= invd[i];
+#pragma unroll
+    for (int i = NS - 1; i >= 0; --i)
+#pragma unroll
+      for (int k = i + 1; k < NS; ++k) x[i] -= L[k][i] * x[k];
+  }
+};
+
+// Ice strength at Gauss point q: P = P* max(0, H Psi) exp(-C (1 - min(1, max(0, A Psi))))
+// (clamps and formula of the stress listings), always in double.
+template <int NA, class Q>
+__device__ __forceinline__ double ice_strength(const KParams &p, const double (&Hc)[NA],
+                                               const double (&Ac)[NA], int q) {
+  double hs = 0.0, as = 0.0;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    hs += Hc[k] * Q::psi(k, q);
+    as += Ac[k] * Q::psi(k, q);
+  }
+  const double h = fmax(0.0, hs);
+  const double a = fmin(1.0, fmax(0.0, as));
+  return p.Pstar * h * exp(-p.C * (1.0 - a));
+}
+
+// ---------------------------------------------------------------------------
+// Element phase: strain -> stress update -> element nodal forces.
+//   T   type of the contractions (double, or float in mixed precision)
+//   TS  storage type of S and of the nodal forces
+// ---------------------------------------------------------------------------
+template <int NS, int NA, class T, class TS>
+__global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p) {
+  using Q = Quad<Ngp<NS>::value>;
+  constexpr int NG = Q::NG;
+  const Blk blk = d.eblk[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int el = blk.first + (int)threadIdx.x;
+  if (el >= D.ne) return;
+  const int ex = el % D.nx, ey = el / D.nx;
+  const size_t ne = (size_t)D.ne;
+
+  const Cell<T> cell = load_cell<T>(D, d.vert, ex, ey);
+  Ldl<NS, T> mass;
+  mass.template build<Q>(cell);
+
+  // ---- strain: gradients of the 9 nodal velocities (shifted by node 0 before
+  // narrowing; the gradient of a constant is zero) ----
+  const double *vxg = d.v + 2 * (size_t)D.node_off;
+  const double *vyg = vxg + D.nn;
+  const int NX = 2 * D.nx + 1;
+  const int j0 = 2 * ey * NX + 2 * ex;
+  T vx[9], vy[9];
+  {
+    const double bx = vxg[j0], by = vyg[j0];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int j = j0 + b * NX + c;
+        vx[3 * b + c] = T(vxg[j] - bx);
+        vy[3 * b + c] = T(vyg[j] - by);
+      }
+  }
+  T E11[NS], E12[NS], E22[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) E11[k] = E12[k] = E22[k] = T(0);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    T gxx = 0, gxe = 0, gyx = 0, gye = 0;  // d/dxi and d/deta of vx, vy
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      if (Q::dxi(a, q) != 0.0) {
+        gxx += T(Q::dxi(a, q)) * vx[a];
+        gyx += T(Q::dxi(a, q)) * vy[a];
+      }
+      if (Q::deta(a, q) != 0.0) {
+        gxe += T(Q::deta(a, q)) * vx[a];
+        gye += T(Q::deta(a, q)) * vy[a];
+      }
+    }
+    T J00, J01, J10, J11;
+    cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+    // w_q |J_q| grad v = w_q adj(J)^T (d/dxi, d/deta) v: the determinant cancels
+    const T w = T(Q::w(q));
+    const T e11 = w * (J11 * gxx - J10 * gxe);
+    const T e22 = w * (J00 * gye - J01 * gyx);
+    const T e12 = T(0.5) * w * ((J00 * gxe - J01 * gxx) + (J11 * gyx - J10 * gye));
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const T ps = T(Q::psi(k, q));
+      E11[k] += ps * e11;
+      E12[k] += ps * e12;
+      E22[k] += ps * e22;
+    }
+  }
+  mass.solve(E11);
+  mass.solve(E12);
+  mass.solve(E22);
+
+  // ---- stress update (Listing 1): Gauss values of E, ice strength, Delta,
+  // P/Delta, the VP stress, its projection and the relaxation ----
+  double Hc[NA], Ac[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    Hc[k] = d.H[((size_t)NA * D.elem_off) + k * ne + el];
+    Ac[k] = d.A[((size_t)NA * D.elem_off) + k * ne + el];
+  }
+  // with one ice dof the strength is constant over the element: one exp per element
+  const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
+  T R11[NS], R12[NS], R22[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    T e11 = 0, e12 = 0, e22 = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const T ps = T(Q::psi(k, q));
+      e11 += E11[k] * ps;
+      e12 += E12[k] * ps;
+      e22 += E22[k] * ps;
+    }
+    const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
+    const double de11 = e11, de12 = e12, de22 = e22;
+    const double D2 = p.dmin2 + 1.25 * (de11 * de11 + de22 * de22) + 1.5 * de11 * de22 + de12 * de12;
+    const double PD = P / sqrt(D2);
+    const T tPD = T(PD), thP = T(0.5 * P);
+    const T s11 = tPD * (T(0.625) * e11 + T(0.375) * e22) - thP;
+    const T s12 = tPD * T(0.25) * e12;
+    const T s22 = tPD * (T(0.625) * e22 + T(0.375) * e11) - thP;
+    T J00, J01, J10, J11;
+    cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+    const T wd = T(Q::w(q)) * (J00 * J11 - J01 * J10);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const T pw = T(Q::psi(k, q)) * wd;
+      R11[k] += pw * s11;
+      R12[k] += pw * s12;
+      R22[k] += pw * s22;
+    }
+  }
+  mass.solve(R11);
+  mass.solve(R12);
+  mass.solve(R22);
+  TS *S = static_cast<TS *>(d.S) + (size_t)3 * NS * D.elem_off;
+  const T fac = T(p.fac), ainv = T(p.ainv);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    R11[k] = fac * T(S[(0 * NS + k) * ne + el]) + ainv * R11[k];
+    R12[k] = fac * T(S[(1 * NS + k) * ne + el]) + ainv * R12[k];
+    R22[k] = fac * T(S[(2 * NS + k) * ne + el]) + ainv * R22[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    S[(0 * NS + k) * ne + el] = TS(R11[k]);
+    S[(1 * NS + k) * ne + el] = TS(R12[k]);
+    S[(2 * NS + k) * ne + el] = TS(R22[k]);
+  }
+
+  // ---- divergence, element part: f[a] = -sum_q w_q |J_q| sigma(q) grad phi_a(q)
+  //      = -sum_q (dphi_a/dxi Gxi + dphi_a/deta Geta) with G = w_q sigma adj(J)^T ----
+  T fx[9], fy[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) fx[a] = fy[a] = T(0);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    T s11 = 0, s12 = 0, s22 = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const T ps = T(Q::psi(k, q));
+      s11 += R11[k] * ps;
+      s12 += R12[k] * ps;
+      s22 += R22[k] * ps;
+    }
+    T J00, J01, J10, J11;
+    cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+    const T w = T(Q::w(q));
+    const T gxxi = w * (s11 * J11 - s12 * J01);
+    const T gxet = w * (s12 * J00 - s11 * J10);
+    const T gyxi = w * (s12 * J11 - s22 * J01);
+    const T gyet = w * (s22 * J00 - s12 * J10);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      if (Q::dxi(a, q) != 0.0) {
+        fx[a] -= T(Q::dxi(a, q)) * gxxi;
+        fy[a] -= T(Q::dxi(a, q)) * gyxi;
+      }
+      if (Q::deta(a, q) != 0.0) {
+        fx[a] -= T(Q::deta(a, q)) * gxet;
+        fy[a] -= T(Q::deta(a, q)) * gyet;
+      }
+    }
+  }
+  TS *fe = static_cast<TS *>(d.fe) + (size_t)18 * D.elem_off;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    fe[a * ne + el] = TS(fx[a]);
+    fe[(9 + a) * ne + el] = TS(fy[a]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Node phase: deterministic gather of the element forces + velocity update.
+// ---------------------------------------------------------------------------
+template <class TF>
+__global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p) {
+  const Blk blk = d.nblk[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int j = blk.first + (int)threadIdx.x;
+  if (j >= D.nn) return;
+  const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
+  const int ix = j % NX, iy = j / NX;
+  double *vx = d.v + 2 * (size_t)D.node_off;
+  double *vy = vx + D.nn;
+  if (ix == 0 || iy == 0 || ix == NX - 1 || iy == NY - 1) {
+    vx[j] = 0.0;
+    vy[j] = 0.0;
+    return;
+  }
+  // elements around node (ix, iy): for an odd index the one element whose
+  // middle node it is, for an even index the elements on both sides
+  const int ney = (iy & 1) ? 1 : 2, nex = (ix & 1) ? 1 : 2;
+  const int ey0 = (iy & 1) ? (iy - 1) / 2 : iy / 2 - 1;
+  const int ex0 = (ix & 1) ? (ix - 1) / 2 : ix / 2 - 1;
+  const int b0 = (iy & 1) ? 1 : 2, c0 = (ix & 1) ? 1 : 2;
+  const TF *fe = static_cast<const TF *>(d.fe) + (size_t)18 * D.elem_off;
+  const size_t ne = (size_t)D.ne;
+  double Fx = 0.0, Fy = 0.0;
+  for (int t = 0; t < ney; ++t) {
+    const int ey = ey0 + t, b = b0 - 2 * t;
+    for (int s = 0; s < nex; ++s) {
+      const int ex = ex0 + s, c = c0 - 2 * s;
+      const size_t e = (size_t)ey * D.nx + ex;
+      const int a = 3 * b + c;
+      Fx += (double)fe[a * ne + e];
+      Fy += (double)fe[(9 + a) * ne + e];
+    }
+  }
+  const size_t o = 2 * (size_t)D.node_off;
+  const double ux = vx[j], uy = vy[j];
+  const double ox = d.ocean[o + j], oy = d.ocean[o + D.nn + j];
+  const double MH = d.MH[D.node_off + j], mA = d.mA[D.node_off + j];
+  const double c = MH * p.inv_dt;
+  const double dox = ox - ux, doy = oy - uy;
+  const double dd = mA * p.rhoCo * sqrt(dox * dox + doy * doy);
+  const double bb = p.f_cor * MH;
+  const double rx = c * (p.beta * ux + d.vn[o + j]) + mA * d.tau[o + j] + dd * ox + Fx;
+  const double ry = c * (p.beta * uy + d.vn[o + D.nn + j]) + mA * d.tau[o + D.nn + j] + dd * oy + Fy;
+  const double aa = c * (1.0 + p.beta) + dd;
+  const double den = aa * aa + bb * bb;
+  if (den == 0.0) {
+    vx[j] = 0.0;
+    vy[j] = 0.0;
+  } else {
+    vx[j] = (aa * rx + bb * ry) / den;
+    vy[j] = (aa * ry - bb * rx) / den;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Start of a time step: v^n, lumped masses (gathered in ascending element
+// order from per-element integrals computed on the fly) and air stress.
+// ---------------------------------------------------------------------------
+template <int NS, int NA>
+__global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams p) {
+  using Q = Quad<Ngp<NS>::value>;
+  const Blk blk = d.nblk[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int j = blk.first + (int)threadIdx.x;
+  if (j >= D.nn) return;
+  const int NX = 2 * D.nx + 1;
+  const int ix = j % NX, iy = j / NX;
+  const size_t o = 2 * (size_t)D.node_off;
+  d.vn[o + j] = d.v[o + j];
+  d.vn[o + D.nn + j] = d.v[o + D.nn + j];
+  const double wx = d.wind[o + j], wy = d.wind[o + D.nn + j];
+  const double sp = sqrt(wx * wx + wy * wy);
+  d.tau[o + j] = p.rhoCa * sp * wx;
+  d.tau[o + D.nn + j] = p.rhoCa * sp * wy;
+
+  double MH = 0.0, mA = 0.0;
+  const size_t ne = (size_t)D.ne;
+  const double *Hd = d.H + (size_t)NA * D.elem_off;
+  const double *Ad = d.A + (size_t)NA * D.elem_off;
+  for (int t = 0; t < 2; ++t) {
+    // candidate element rows: iy odd -> (iy-1)/2 only; iy even -> iy/2-1 and iy/2
+    const int ey = (iy & 1) ? ((t == 0) ? (iy - 1) / 2 : -1) : iy / 2 - 1 + t;
+    if (ey < 0 || ey >= D.ny) continue;
+    const int b = iy - 2 * ey;
+    for (int s = 0; s < 2; ++s) {
+      const int ex = (ix & 1) ? ((s == 0) ? (ix - 1) / 2 : -1) : ix / 2 - 1 + s;
+      if (ex < 0 || ex >= D.nx) continue;
+      const int cc = ix - 2 * ex;
+      const int a = 3 * b + cc;
+      const size_t e = (size_t)ey * D.nx + ex;
+      const Cell<double> cell = load_cell<double>(D, d.vert, ex, ey);
+      double Hc[NA], Ac[NA];
+#pragma unroll
+      for (int k = 0; k < NA; ++k) {
+        Hc[k] = Hd[k * ne + e];
+        Ac[k] = Ad[k * ne + e];
+      }
+      double sh = 0.0, sa = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q::NG; ++q) {
+        double J00, J01, J10, J11;
+        cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+        const double wd = Q::w(q) * (J00 * J11 - J01 * J10);
+        double hs = 0.0, as = 0.0;
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          hs += Hc[k] * Q::psi(k, q);
+          as += Ac[k] * Q::psi(k, q);
+        }
+        const double h = fmax(0.0, hs), ac = fmin(1.0, fmax(0.0, as));
+        double phi = 0.0;
+        switch (a) {  // keep the table lookup a constant per branch
+#define MEVP_PHI_CASE(A_) case A_: phi = Q::phi(A_, q); break;
+          MEVP_PHI_CASE(0) MEVP_PHI_CASE(1) MEVP_PHI_CASE(2) MEVP_PHI_CASE(3) MEVP_PHI_CASE(4)
+          MEVP_PHI_CASE(5) MEVP_PHI_CASE(6) MEVP_PHI_CASE(7) MEVP_PHI_CASE(8)
+#undef MEVP_PHI_CASE
+        }
+        sh += wd * p.rho_i * h * phi;
+        sa += wd * ac * phi;
+      }
+      MH += sh;
+      mA += sa;
+    }
+  }
+  d.MH[D.node_off + j] = MH;
+  d.mA[D.node_off + j] = mA;
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill(uint32_t *dst, size_t n, uint32_t value) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = value;
+}
+__global__ void k_d2f(const double *src, float *dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+__global__ void k_f2d(const float *src, double *dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+template <class T>
+__global__ void k_check_finite(const T *p, size_t n, int *flag, int bit) {
+  int bad = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(p[i]);
+  if (bad) atomicOr(flag, bit);
+}
+template <int NS>
+__global__ void __launch_bounds__(kElemBlock) k_check_jacobian(DevArrays d, int bit) {
+  using Q = Quad<Ngp<NS>::value>;
+  const Blk blk = d.eblk[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int el = blk.first + (int)threadIdx.x;
+  if (el >= D.ne) return;
+  const Cell<double> c = load_cell<double>(D, d.vert, el % D.nx, el / D.nx);
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < Q::NG; ++q) {
+    double J00, J01, J10, J11;
+    c.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+    bad |= !(J00 * J11 - J01 * J10 > 0.0);
+  }
+  if (bad) atomicOr(d.flag, bit);
+}
+
+inline unsigned grid_for(size_t n, unsigned block) {
+  size_t g = (n + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g == 0) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int NS, int NA>
+static hipError_t begin_step_t(const DevArrays &d, const KParams &p, int n_nblk, hipStream_t s) {
+  hipLaunchKernelGGL((k_begin_step<NS, NA>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int n_s, int n_nblk,
+                             hipStream_t s) {
+#define MEVP_BS(NS_, NA_) \
+  if (n_s == NS_ && n_a == NA_) return begin_step_t<NS_, NA_>(d, p, n_nblk, s);
+  MEVP_BS(3, 1) MEVP_BS(3, 3) MEVP_BS(3, 6)
+  MEVP_BS(6, 1) MEVP_BS(6, 3) MEVP_BS(6, 6)
+  MEVP_BS(8, 1) MEVP_BS(8, 3) MEVP_BS(8, 6)
+#undef MEVP_BS
+  return hipErrorInvalidValue;
+}
+
+template <int NS, int NA>
+static hipError_t element_t(const DevArrays &d, const KParams &p, bool mixed, int n_eblk,
+                            hipStream_t s) {
+  if (mixed)
+    hipLaunchKernelGGL((k_element<NS, NA, float, float>), dim3(n_eblk), dim3(kElemBlock), 0, s, d, p);
+  else
+    hipLaunchKernelGGL((k_element<NS, NA, double, double>), dim3(n_eblk), dim3(kElemBlock), 0, s, d, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, int n_a, bool mixed,
+                                int n_eblk, hipStream_t s) {
+#define MEVP_EL(NS_, NA_) \
+  if (n_s == NS_ && n_a == NA_) return element_t<NS_, NA_>(d, p, mixed, n_eblk, s);
+  MEVP_EL(3, 1) MEVP_EL(3, 3) MEVP_EL(3, 6)
+  MEVP_EL(6, 1) MEVP_EL(6, 3) MEVP_EL(6, 6)
+  MEVP_EL(8, 1) MEVP_EL(8, 3) MEVP_EL(8, 6)
+#undef MEVP_EL
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, int n_nblk,
+                             hipStream_t s) {
+  if (mixed)
+    hipLaunchKernelGGL((k_node<float>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p);
+  else
+    hipLaunchKernelGGL((k_node<double>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void *dst, size_t n_words32, uint32_t value, hipStream_t s) {
+  if (n_words32 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n_words32, 256)), dim3(256), 0, s,
+                     static_cast<uint32_t *>(dst), n_words32, value);
+  return hipGetLastError();
+}
+hipError_t launch_convert_d2f(const double *src, float *dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_d2f, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_convert_f2d(const float *src, double *dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_f2d, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_check_finite(const double *p, size_t n, int *flag, int bit, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_check_finite<double>), dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, flag, bit);
+  return hipGetLastError();
+}
+hipError_t launch_check_finite_f(const float *p, size_t n, int *flag, int bit, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_check_finite<float>), dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, flag, bit);
+  return hipGetLastError();
+}
+hipError_t launch_check_jacobian(const DevArrays &d, int n_s, int n_eblk, int bit, hipStream_t s) {
+  if (n_s == 3)
+    hipLaunchKernelGGL((k_check_jacobian<3>), dim3(n_eblk), dim3(kElemBlock), 0, s, d, bit);
+  else
+    hipLaunchKernelGGL((k_check_jacobian<6>), dim3(n_eblk), dim3(kElemBlock), 0, s, d, bit);
+  return hipGetLastError();
+}
+
+}  // namespace mevp

@@ -35,11 +35,14 @@ __all__ = [
     "ocean_field",
     "make_domain",
     "batched_sizes",
-    "CONFIG_SEEDS",
+    "WORKLOAD_SEEDS",
+    "named_workload",
+    "random_state",
 ]
 
-#: seeds of the named workloads (single domains); the batched workload uses 466
-CONFIG_SEEDS = {"c1": 1001, "c2": 1002, "c3": 1003, "c5": 1005, "c4": 466}
+#: seeds of the named workloads; the batched one derives per-domain seeds from 466
+WORKLOAD_SEEDS = {"32x32-dg1": 1001, "256x256-dg2": 1002, "1024x1024-dg2": 1003,
+                  "2048x2048-dg2": 1005, "batch64-dg2": 466}
 
 #: wind gyre peak speed [m/s], angular rotation rate [1/s], ocean peak [m/s]
 WIND_PEAK = 10.0
@@ -182,18 +185,42 @@ def batched_sizes(seed: int = 466, n_domains: int = 64, lo: int = 64, hi: int = 
 
 
 def named_workload(name: str) -> list[DomainInputs]:
-    """The five named workloads as lists of domains (one entry unless batched)."""
-    name = name.lower()
-    if name == "c1":
-        return [make_domain(32, 32, 3, 1, CONFIG_SEEDS["c1"], h=10e3)]
-    if name == "c2":
-        return [make_domain(256, 256, 6, 1, CONFIG_SEEDS["c2"])]
-    if name == "c3":
-        return [make_domain(1024, 1024, 6, 1, CONFIG_SEEDS["c3"])]
-    if name == "c5":
-        return [make_domain(2048, 2048, 6, 1, CONFIG_SEEDS["c5"])]
-    if name == "c4":
-        sizes, phases = batched_sizes(CONFIG_SEEDS["c4"])
-        return [make_domain(n, n, 6, 1, 1000 * CONFIG_SEEDS["c4"] + d, wind_phase=phases[d])
+    """A named workload as a list of domains (one entry unless batched):
+      32x32-dg1       32 x 32 cells of 10 km, 3 stress dofs (2x2 Gauss)
+      256x256-dg2     256 x 256 cells on a 512 km square (2 km), 6 stress dofs
+      1024x1024-dg2   1024 x 1024 cells on 512 km (0.5 km)
+      2048x2048-dg2   2048 x 2048 cells on 512 km (0.25 km)
+      batch64-dg2     64 square domains of 512 km, sides 64..512 cells (seeded)
+    """
+    seed = WORKLOAD_SEEDS[name]
+    if name == "32x32-dg1":
+        return [make_domain(32, 32, 3, 1, seed, h=10e3)]
+    if name == "batch64-dg2":
+        sizes, phases = batched_sizes(seed)
+        return [make_domain(n, n, 6, 1, 1000 * seed + d, wind_phase=phases[d])
                 for d, n in enumerate(sizes)]
-    raise ValueError(f"unknown workload {name!r}")
+    n = int(name.split("x")[0])
+    return [make_domain(n, n, 6, 1, seed)]
+
+
+def random_state(nx: int, ny: int, n_s: int, seed: int, v_scale: float = 0.01,
+                 s_scale: float = 5000.0):
+    """A seeded mid-iteration state (v, S) for tests that start from a state
+    other than rest: a smooth velocity gyre of ``v_scale`` m/s plus 1% noise,
+    zero on the outer boundary, and DG stress coefficients of magnitude
+    ``s_scale`` N/m (higher-order coefficients smaller)."""
+    rng = np.random.default_rng(seed)
+    xh, yh = _node_logical(nx, ny)
+    bump = np.sin(math.pi * xh) * np.sin(math.pi * yh)
+    vx = v_scale * (bump * np.cos(3.0 * yh) + 0.01 * rng.standard_normal(xh.shape))
+    vy = v_scale * (-bump * np.sin(2.0 * xh) + 0.01 * rng.standard_normal(xh.shape))
+    NX, NY = 2 * nx + 1, 2 * ny + 1
+    ix, iy = np.arange(NX * NY) % NX, np.arange(NX * NY) // NX
+    edge = (ix == 0) | (iy == 0) | (ix == NX - 1) | (iy == NY - 1)
+    vx[edge] = 0.0
+    vy[edge] = 0.0
+    decay = np.array([1.0, 0.3, 0.3, 0.1, 0.1, 0.1, 0.03, 0.03])[:n_s]
+    S = s_scale * rng.standard_normal((3, n_s, nx * ny)) * decay[None, :, None]
+    S[0, 0] -= s_scale
+    S[2, 0] -= s_scale
+    return np.stack([vx, vy]).astype(np.float64), S

@@ -1,0 +1,138 @@
+"""CPU tests of the C ABI: the library loads, exports every declared symbol, and
+rejects bad arguments on the host before any device work (no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_2402_00466_amd as M
+    M.lib()
+    return M
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "mevp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mevp_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(M):
+    syms = _declared_symbols()
+    assert len(syms) >= 18
+    L = C.CDLL(M.lib_path())
+    for s in syms:
+        assert hasattr(L, s), f"{s} declared in mevp.h but not exported"
+    assert sorted(M.EXPORTS) == syms
+
+
+def test_library_links_no_oracle_and_no_torch(M):
+    """The product library is self-contained HIP: it must not depend on the oracle or torch."""
+    import subprocess
+    out = subprocess.run(["ldd", M.lib_path()], capture_output=True, text=True).stdout
+    names = [line.split()[0] for line in out.splitlines() if line.strip()]
+    assert not any("oracle" in n or "torch" in n or n.startswith("libc10") for n in names), names
+    assert any(n.startswith("libamdhip64") for n in names), names
+
+
+def test_default_params_match_paper_values(M):
+    p = M.default_params()
+    assert p.Pstar == 27500.0 and p.C == 20.0 and p.alpha == 300.0 and p.beta == 300.0
+    assert p.dt == 120.0 and p.relax_form == 0
+    assert M.Params() == p
+
+
+def test_workspace_size_valid_and_monotone(M):
+    D = M.Domain
+    a = M.workspace_size([D(32, 32, 3, 1)])
+    b = M.workspace_size([D(64, 32, 3, 1)])
+    c = M.workspace_size([D(64, 32, 3, 1)], "mixed")
+    e = M.workspace_size([D(64, 32, 6, 1), D(17, 5, 6, 1)])
+    assert 0 < a < b and c < b and e > M.workspace_size([D(64, 32, 6, 1)])
+    assert a % 256 == 0
+
+
+@pytest.mark.parametrize("doms", [
+    [(0, 4, 6, 1)], [(4, -1, 6, 1)], [(4, 4, 5, 1)], [(4, 4, 6, 2)], [(4, 4, 6, 1), (4, 4, 3, 1)],
+    [(4, 4, 6, 1), (4, 4, 6, 3)], [(70000, 70000, 6, 1)]])
+def test_workspace_size_rejects_bad_domains(M, doms):
+    with pytest.raises(M.MevpError) as ei:
+        M.workspace_size([M.Domain(*d) for d in doms])
+    assert ei.value.status == -1
+
+
+def test_null_and_empty_arguments(M):
+    L = M.lib()
+    out = C.c_size_t(0)
+    assert L.mevp_workspace_size(None, 1, 0, C.byref(out)) == -1
+    arr = (M.mevp.CDomain * 1)(M.mevp.CDomain(4, 4, 6, 1))
+    assert L.mevp_workspace_size(arr, 0, 0, C.byref(out)) == -1
+    assert L.mevp_workspace_size(arr, 1, 7, C.byref(out)) == -1   # bad precision
+    assert L.mevp_workspace_size(arr, 1, 0, None) == -1
+    assert L.mevp_default_params(None) == -1
+    # every context call rejects a NULL context
+    for f, args in [("mevp_set_geometry", (0, None)), ("mevp_set_fields", (0, None, None)),
+                    ("mevp_set_forcing", (0, None, None)), ("mevp_set_state", (0, None, None)),
+                    ("mevp_step", (1,)), ("mevp_begin_step", ()), ("mevp_subcycles", (1,)),
+                    ("mevp_get_state", (0, None, None)), ("mevp_sync", ()),
+                    ("mevp_check_inputs", ()), ("mevp_check_state", ())]:
+        assert getattr(L, f)(None, *args) == -1, f
+    L.mevp_destroy(None)  # no-op
+
+
+def _create(M, params=None, ws=0x10000000, ws_bytes=None, doms=((8, 8, 6, 1),), prec=0):
+    L = M.lib()
+    arr = (M.mevp.CDomain * len(doms))(*[M.mevp.CDomain(*d) for d in doms])
+    if ws_bytes is None:
+        ws_bytes = M.workspace_size([M.Domain(*d) for d in doms])
+    p = (params or M.Params()).to_c()
+    h = C.c_void_p()
+    return L.mevp_create(C.byref(p), prec, arr, len(doms), C.c_void_p(ws), C.c_size_t(ws_bytes),
+                         None, C.byref(h))
+
+
+@pytest.mark.parametrize("field,value", [("alpha", 0.0), ("dt", -1.0), ("DeltaMin", 0.0),
+                                         ("beta", -1.0), ("Pstar", float("nan")),
+                                         ("C", float("inf")), ("rho_i", 0.0), ("relax_form", 2)])
+def test_create_rejects_bad_params_before_device(M, field, value):
+    p = M.Params()
+    setattr(p, field, value)
+    assert _create(M, params=p) == -1
+
+
+def test_create_rejects_workspace_problems_before_device(M):
+    assert _create(M, ws=0) == -1                 # NULL workspace
+    assert _create(M, ws=0x10000000 + 8) == -1    # not 256-byte aligned
+    need = M.workspace_size([M.Domain(8, 8, 6, 1)])
+    assert _create(M, ws_bytes=need - 1) == -2    # too small
+    assert _create(M, ws_bytes=1 << 20, doms=((8, 8, 6, 1), (8, 8, 3, 1))) == -1
+
+
+def test_create_without_device_reports_device_error(M):
+    """All host checks pass; with no GPU the first runtime call fails -> EDEVICE, never a crash."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present; the fake workspace pointer must not reach it")
+    assert _create(M) == -3
+
+
+def test_status_strings(M):
+    L = M.lib()
+    for s, text in [(0, "ok"), (-1, "invalid argument"), (-2, "workspace too small"),
+                    (-3, "device error"), (-4, "call out of order"), (-6, "unsupported device")]:
+        assert L.mevp_status_string(s).decode() == text
+    assert L.mevp_status_string(99).decode() == "unknown status"
+    assert L.mevp_version().decode().startswith("mevp-gfx950")
+
+
+def test_binding_fails_loudly_without_library(M, monkeypatch, tmp_path):
+    import paper_2402_00466_amd.mevp as mm
+    monkeypatch.setattr(mm, "_lib", None)
+    monkeypatch.setattr(mm._build, "LIB", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        mm.lib()

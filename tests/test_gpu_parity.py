@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (per field, normwise max|x - ref| / max|ref|, over v_x, v_y, S11,
+S12, S22): FP64 <= 1e-12, mixed precision <= 1e-5.
+
+The mEVP iteration with alpha = beta = 300 amplifies rounding differences by
+about 1.25x per subcycle once cells are finer than ~8 km (measured with the
+oracle alone: a 1e-15 relative change of H grows to 1e-8..1e-6 after 100
+subcycles at 0.25-2 km). Two independently rounded FP64 programs therefore
+agree to 1e-12 over a whole time step only on coarse meshes. The tests below
+check (a) whole runs where that holds (10 km and coarser test meshes, up to
+several time steps) and (b) a few subcycles from the same seeded state at
+every workload size, including 2048 x 2048, where the amplification is
+bounded by ~2x. Fine-mesh whole-run differences are compared with the
+oracle's own sensitivity in test_gpu_sensitivity.py.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import field_errors, gpu_run, log, oracle_params, oracle_run
+from synth_inputs import make_domain, named_workload, random_state
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOLMIX = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_2402_00466_amd as M
+    M.lib()
+
+
+def _assert_close(errs, tol, what):
+    log(f"{what}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{what}: fields over {tol:g}: {bad}"
+
+
+# (nx, ny, n_s, n_a, h [m], perturb, ho_amp, n_steps, n_sub)
+WHOLE_RUNS = [
+    (12, 10, 6, 1, 10e3, 0.10, 0.0, 2, 20),     # bilinear cells, 2 steps
+    (33, 17, 3, 1, 10e3, 0.00, 0.0, 1, 100),    # 561 elements: 3 element blocks, ragged tail
+    (40, 23, 6, 3, 12e3, 0.15, 0.3, 2, 30),     # n_a = 3, active clamps
+    (19, 26, 6, 6, 10e3, 0.05, 0.2, 1, 50),     # n_a = 6
+    (9, 7, 8, 1, 10e3, 0.10, 0.0, 1, 40),       # n_s = 8
+    (1, 1, 6, 1, 10e3, 0.00, 0.0, 1, 10),       # one element: only the centre node moves
+    (1, 37, 3, 1, 10e3, 0.00, 0.0, 1, 25),      # one element wide
+    (300, 2, 6, 1, 10e3, 0.00, 0.0, 1, 25),     # two elements tall, 600 elements
+]
+
+
+@pytest.mark.parametrize("case", WHOLE_RUNS, ids=lambda c: "x".join(map(str, c[:4])))
+def test_whole_run_fp64(case):
+    nx, ny, ns, na, h, pert, ho, steps, nsub = case
+    d = make_domain(nx, ny, ns, na, seed=nx * 100 + ny, h=h, perturb=pert, ho_amp=ho)
+    if nx == 1 and ny == 1:
+        # the gyre and the current vanish at the single interior node: drive it with a
+        # uniform wind so that v and S12 are not pure rounding noise
+        d.wind[0], d.wind[1] = 4.0, -3.0
+    log(f"case {case}")
+    (v, S), = gpu_run([d], steps, nsub)
+    vr, Sr = oracle_run(d, steps, nsub)
+    _assert_close(field_errors(v, S, vr, Sr), TOL64, f"fp64 {nx}x{ny} ns={ns} na={na}")
+
+
+def test_whole_run_32x32_dg1_workload():
+    """32 x 32 cells of 10 km, 3 stress dofs, 1 step x 100 subcycles: the whole run."""
+    d, = named_workload("32x32-dg1")
+    (v, S), = gpu_run([d], 1, 100)
+    vr, Sr = oracle_run(d, 1, 100)
+    assert np.abs(vr).max() > 1e-3  # the ice moved
+    _assert_close(field_errors(v, S, vr, Sr), TOL64, "32x32-dg1 fp64")
+    (vm, Sm), = gpu_run([d], 1, 100, precision="mixed")
+    _assert_close(field_errors(vm, Sm, vr, Sr), TOLMIX, "32x32-dg1 mixed")
+
+
+def test_whole_run_mixed_small():
+    d = make_domain(40, 23, 6, 3, seed=7, h=12e3, perturb=0.15, ho_amp=0.3)
+    (v, S), = gpu_run([d], 2, 30, precision="mixed")
+    vr, Sr = oracle_run(d, 2, 30)
+    _assert_close(field_errors(v, S, vr, Sr), TOLMIX, "mixed 40x23")
+
+
+def _few_subcycles(name, n_sub, precision, tol, dom_index=0):
+    d = named_workload(name)[dom_index]
+    state = random_state(d.nx, d.ny, d.n_s, seed=99)
+    log(f"workload {name} domain {dom_index} ({d.nx}x{d.ny}) {precision} {n_sub} subcycles from a seeded state")
+    (v, S), = gpu_run([d], 1, n_sub, precision=precision, states=[state])
+    vr, Sr = oracle_run(d, 1, n_sub, state=state)
+    _assert_close(field_errors(v, S, vr, Sr), tol, f"{name} {precision} {n_sub} subcycles")
+
+
+@pytest.mark.parametrize("name", ["256x256-dg2", "1024x1024-dg2", "2048x2048-dg2"])
+def test_few_subcycles_full_size_fp64(name):
+    _few_subcycles(name, 3, "fp64", TOL64)
+
+
+@pytest.mark.parametrize("name", ["256x256-dg2", "1024x1024-dg2", "2048x2048-dg2"])
+def test_few_subcycles_full_size_mixed(name):
+    _few_subcycles(name, 3, "mixed", TOLMIX)
+
+
+def test_batched_equals_solo_bitwise_and_matches_oracle():
+    """Domains of uneven sizes in one context give bit-identical results to each
+    domain alone, and each matches the oracle."""
+    doms = [make_domain(n, m, 6, 1, seed=500 + n, h=10e3, perturb=0.1 if n % 2 else 0.0)
+            for n, m in [(17, 9), (64, 31), (5, 40), (33, 33), (1, 1), (100, 3)]]
+    doms[4].wind[0], doms[4].wind[1] = 4.0, -3.0  # see test_whole_run_fp64
+    batched = gpu_run(doms, 2, 15)
+    for k, d in enumerate(doms):
+        (v, S), = gpu_run([d], 2, 15)
+        assert np.array_equal(v, batched[k][0]) and np.array_equal(S, batched[k][1]), k
+        vr, Sr = oracle_run(d, 2, 15)
+        _assert_close(field_errors(v, S, vr, Sr), TOL64, f"batched domain {k} ({d.nx}x{d.ny})")
+
+
+def test_batch64_workload_subset_at_first_step():
+    """The 64-domain batched workload in one context: domains against the oracle
+    (a few subcycles from rest, all domains), bitwise against solo runs for two."""
+    doms = named_workload("batch64-dg2")
+    res = gpu_run(doms, 1, 3)
+    for k in [0, 1, 17, 40, 63]:
+        vr, Sr = oracle_run(doms[k], 1, 3)
+        _assert_close(field_errors(*res[k], vr, Sr), TOL64, f"batch64 domain {k} ({doms[k].nx}^2)")
+    for k in [0, 63]:
+        (v, S), = gpu_run([doms[k]], 1, 3)
+        assert np.array_equal(v, res[k][0]) and np.array_equal(S, res[k][1])
+
+
+def test_deterministic_bitwise():
+    d = make_domain(70, 50, 6, 1, seed=3, h=2e3, perturb=0.1)
+    a = gpu_run([d], 2, 30)[0]
+    b = gpu_run([d], 2, 30)[0]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    c = gpu_run([d], 2, 30, precision="mixed")[0]
+    e = gpu_run([d], 2, 30, precision="mixed")[0]
+    assert np.array_equal(c[0], e[0]) and np.array_equal(c[1], e[1])
+
+
+def test_checkpoint_resume_bitwise():
+    """State after k steps, restored into a fresh context, continues bit-identically."""
+    d = make_domain(30, 20, 6, 1, seed=8, h=4e3)
+    full = gpu_run([d], 3, 20)[0]
+    first = gpu_run([d], 2, 20)[0]
+    resumed = gpu_run([d], 1, 20, states=[first])[0]
+    assert np.array_equal(full[0], resumed[0]) and np.array_equal(full[1], resumed[1])
+
+
+def test_zero_subcycles_and_subcycles_without_snapshot():
+    import paper_2402_00466_amd as M
+    d = make_domain(8, 6, 6, 1, seed=5, h=10e3)
+    state = random_state(8, 6, 6, seed=1)
+    (v, S), = gpu_run([d], 1, 0, states=[state])
+    assert np.array_equal(v, state[0]) and np.array_equal(S, state[1])
+    # subcycles without begin_step use the last snapshot: matches the oracle's subcycles
+    import oracle
+    m = oracle.Mesh(d.nx, d.ny, d.n_s, d.n_a, d.vertices)
+    vr, Sr = m.step(oracle.Params(), d.H, d.A, d.wind, d.ocean, state[0], state[1], 7)
+    import torch
+    ctx = M.Context([M.Domain(8, 6, 6, 1)])
+    ctx.upload(0, d)
+    ctx.set_state(0, torch.as_tensor(state[0]).cuda(), torch.as_tensor(state[1]).cuda())
+    ctx.begin_step()
+    ctx.subcycles(3)
+    ctx.subcycles(4)
+    v2, S2 = ctx.get_state(0)
+    ctx.sync()
+    _assert_close(field_errors(v2.cpu().numpy(), S2.cpu().numpy(), vr, Sr), TOL64, "split subcycles")
+
+
+def test_equation_relaxation_form():
+    """relax_form = 1: alpha/(1+alpha), 1/(1+alpha) of Eq. (si:mevp) instead of the
+    listings' (1-1/alpha), 1/alpha. The two forms differ by far more than the tolerance."""
+    import paper_2402_00466_amd as M
+    mp = M.Params(relax_form=1)
+    d = make_domain(15, 11, 6, 1, seed=4, h=10e3, perturb=0.1)
+    (v, S), = gpu_run([d], 1, 40, params=mp)
+    vr, Sr = oracle_run(d, 1, 40, params=oracle_params(mp))
+    _assert_close(field_errors(v, S, vr, Sr), TOL64, "relax_form=1")
+    v0, S0 = oracle_run(d, 1, 40)
+    assert max(field_errors(v0, S0, vr, Sr).values()) > 1e-6
