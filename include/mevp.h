@@ -119,7 +119,10 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
 mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params);
 
 /* Copy-in calls (stream-ordered; the caller may reuse its buffer once the
- * stream has passed the call). Layouts as above. */
+ * stream has passed the call). Layouts as above. mevp_set_geometry also
+ * classifies the cells of the domain (all parallelograms or not, which picks
+ * the element kernel; Sec. 2.1: cells are mapped from a reference element) and
+ * waits for the stream to do so. */
 mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy);
 mevp_status mevp_set_fields(mevp_ctx *ctx, int dom, const double *H, const double *A);
 mevp_status mevp_set_forcing(mevp_ctx *ctx, int dom, const double *wind_xy,

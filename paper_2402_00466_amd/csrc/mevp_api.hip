@@ -25,6 +25,8 @@ struct mevp_ctx {
   std::vector<mevp_domain_desc> desc;
   std::vector<DomDev> dom_h;
   std::vector<Blk> eblk_h, nblk_h;
+  std::vector<unsigned char> affine;  // per domain: every cell a parallelogram
+  int n_aff = 0;                      // leading element blocks of affine domains
   DevArrays d{};
   DomDev *doms_d = nullptr;
   Blk *eblk_d = nullptr, *nblk_d = nullptr;
@@ -77,13 +79,13 @@ KParams derive(const mevp_params &p) {
   k.rho_i = p.rho_i;
   k.rhoCa = p.rho_a * p.C_a;
   k.rhoCo = p.rho_o * p.C_o;
-  k.f_cor = p.f_cor;
+  k.f_dt = p.f_cor * p.dt;
   return k;
 }
 
 // Layout of the workspace: offsets in bytes of every array.
 struct Layout {
-  size_t doms, eblk, nblk, flag, vert, H, A, wind, ocean, v, vn, tau, MH, mA, S, fe, total;
+  size_t doms, eblk, nblk, flag, vert, H, A, wind, ocean, v, nc, S, fe, total;
   size_t tot_e, tot_n, tot_v;
   int n_eblk, n_nblk;
   int ns, na;
@@ -127,10 +129,7 @@ mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout
   L->wind = take(sizeof(double) * 2 * tn);
   L->ocean = take(sizeof(double) * 2 * tn);
   L->v = take(sizeof(double) * 2 * tn);
-  L->vn = take(sizeof(double) * 2 * tn);
-  L->tau = take(sizeof(double) * 2 * tn);
-  L->MH = take(sizeof(double) * tn);
-  L->mA = take(sizeof(double) * tn);
+  L->nc = take(sizeof(double) * 6 * tn);
   L->S = take(ws * 3 * ns * te);
   L->fe = take(ws * 18 * te);
   L->total = off;
@@ -175,6 +174,19 @@ void timer_stop(mevp_ctx *c, int ph, int slot) {
   if (slot < 0) return;
   auto &t = c->timer[ph];
   if (hipEventRecord(t.ev[2 * slot + 1], c->stream) == hipSuccess) t.used = slot + 1;
+}
+
+// Element blocks with the domains of parallelogram cells first (one launch of
+// the affine kernel), then the rest (one launch of the general kernel).
+void order_blocks(mevp_ctx *c) {
+  c->eblk_h.clear();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i < c->nd; ++i) {
+      if ((pass == 0) != (c->affine[i] != 0)) continue;
+      for (int f = 0; f < c->dom_h[i].ne; f += kElemBlock) c->eblk_h.push_back(Blk{i, f});
+    }
+    if (pass == 0) c->n_aff = (int)c->eblk_h.size();
+  }
 }
 
 }  // namespace
@@ -258,6 +270,7 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
   c->tot_n = L.tot_n;
   c->tot_v = L.tot_v;
   c->geo_set.assign(n_domains, 0);
+  c->affine.assign(n_domains, 0);
   c->fld_set.assign(n_domains, 0);
   c->frc_set.assign(n_domains, 0);
 
@@ -277,9 +290,9 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
     no += D.nn;
     vo += D.nv;
     c->dom_h.push_back(D);
-    for (int f = 0; f < D.ne; f += kElemBlock) c->eblk_h.push_back(Blk{i, f});
     for (int f = 0; f < D.nn; f += kNodeBlock) c->nblk_h.push_back(Blk{i, f});
   }
+  order_blocks(c);
 
   char *base = static_cast<char *>(workspace);
   c->doms_d = reinterpret_cast<DomDev *>(base + L.doms);
@@ -296,10 +309,7 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
   d.wind = reinterpret_cast<double *>(base + L.wind);
   d.ocean = reinterpret_cast<double *>(base + L.ocean);
   d.v = reinterpret_cast<double *>(base + L.v);
-  d.vn = reinterpret_cast<double *>(base + L.vn);
-  d.tau = reinterpret_cast<double *>(base + L.tau);
-  d.MH = reinterpret_cast<double *>(base + L.MH);
-  d.mA = reinterpret_cast<double *>(base + L.mA);
+  d.nc = reinterpret_cast<double *>(base + L.nc);
   d.S = base + L.S;
   d.fe = base + L.fe;
 
@@ -332,10 +342,26 @@ mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params) {
 mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy) {
   if (bad_dom(ctx, dom) || !vertex_xy) return MEVP_EINVAL;
   const DomDev &D = ctx->dom_h[dom];
+  hipStream_t s = ctx->stream;
   mevp_status st = copy(const_cast<double *>(ctx->d.vert) + 2 * (size_t)D.vert_off, vertex_xy,
-                        sizeof(double) * 2 * D.nv, ctx->stream);
-  if (st == MEVP_OK) ctx->geo_set[dom] = 1;
-  return st;
+                        sizeof(double) * 2 * D.nv, s);
+  // classify the cells: all parallelograms -> the constant-Jacobian kernel
+  int *flag = ctx->d.flag + 1;
+  if (st == MEVP_OK) st = hip_status(launch_fill(flag, 1, 1u, s));
+  if (st == MEVP_OK) st = hip_status(launch_cell_shape(ctx->d, dom, D.ne, flag, s));
+  int aff = 0;
+  if (st == MEVP_OK) st = hip_status(hipMemcpyAsync(&aff, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(s));
+  if (st != MEVP_OK) return st;
+  if ((aff != 0) != (ctx->affine[dom] != 0)) {
+    ctx->affine[dom] = aff != 0;
+    order_blocks(ctx);
+    st = copy(ctx->eblk_d, ctx->eblk_h.data(), sizeof(Blk) * ctx->eblk_h.size(), s);
+    if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(s));
+    if (st != MEVP_OK) return st;
+  }
+  ctx->geo_set[dom] = 1;
+  return MEVP_OK;
 }
 
 mevp_status mevp_set_fields(mevp_ctx *ctx, int dom, const double *H, const double *A) {
@@ -419,8 +445,8 @@ mevp_status mevp_subcycles(mevp_ctx *ctx, int n) {
   const bool mixed = ctx->prec == MEVP_MIXED;
   for (int it = 0; it < n; ++it) {
     int slot = timer_start(ctx, 0);
-    hipError_t e = launch_element_phase(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed,
-                                        (int)ctx->eblk_h.size(), ctx->stream);
+    hipError_t e = launch_element_phase(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->n_aff,
+                                        (int)ctx->eblk_h.size() - ctx->n_aff, ctx->stream);
     timer_stop(ctx, 0, slot);
     if (e == hipSuccess) {
       slot = timer_start(ctx, 1);

@@ -29,13 +29,13 @@ struct KParams {
   double Pstar, C, dmin2;  // P*, concentration factor, Delta_min^2
   double fac, ainv;        // stress relaxation weights
   double beta, inv_dt;     // velocity relaxation, 1/dt
-  double rho_i, rhoCa, rhoCo, f_cor;
+  double rho_i, rhoCa, rhoCo, f_dt;  // densities x drag coefficients, Coriolis x dt
 };
 
 // Device pointers of one context (all carved from the caller's workspace).
 struct DevArrays {
   const DomDev *doms;
-  const Blk *eblk;  // element blocks
+  const Blk *eblk;  // element blocks: parallelogram-cell domains first, then general
   const Blk *nblk;  // node blocks
   const double *vert;  // [dom][2][nv]
   const double *H;     // [dom][n_a][ne]
@@ -43,10 +43,7 @@ struct DevArrays {
   const double *wind;  // [dom][2][nn]
   const double *ocean;
   double *v;           // [dom][2][nn]
-  double *vn;          // [dom][2][nn] velocity at the start of the step
-  double *tau;         // [dom][2][nn] air stress
-  double *MH;          // [dom][nn] lumped ice mass
-  double *mA;          // [dom][nn] lumped concentration
+  double *nc;          // [dom][6][nn] node constants of the velocity update
   void *S;             // [dom][3][n_s][ne], double or float
   void *fe;            // [dom][18][ne] element nodal forces, double or float
   int *flag;           // check results
@@ -59,7 +56,8 @@ constexpr int kNodeBlock = 256;
 hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int n_s,
                              int n_nblk, hipStream_t s);
 hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, int n_a,
-                                bool mixed, int n_eblk, hipStream_t s);
+                                bool mixed, int n_aff, int n_gen, hipStream_t s);
+hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s);
 hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, int n_nblk,
                              hipStream_t s);
 hipError_t launch_fill(void *dst, size_t n_words32, uint32_t value, hipStream_t s);

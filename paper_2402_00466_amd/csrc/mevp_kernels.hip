@@ -3,18 +3,19 @@
 // One subcycle (Table 1 of the paper: strain, stress, divergence, velocity)
 // is two launches:
 //   element phase  one element per lane: gather the 9 CG2 velocities, strain
-//                  rates at the Gauss points, L2 projection onto the DG stress
-//                  space, the VP stress update of Listing 1 (S read and
-//                  written once), the new stress at the Gauss points and the
-//                  weak-form nodal forces of the element (18 values, written
-//                  to a scratch array, element-fastest);
+//                  rates, L2 projection onto the DG stress space, the VP stress
+//                  update of Listing 1 (S read and written once), the new
+//                  stress and the weak-form nodal forces of the element
+//                  (18 values, written to a scratch array, element-fastest).
+//                  Two kernels: parallelogram cells (constant Jacobian,
+//                  diagonal mass matrix, strain and divergence as exact
+//                  constant operators) and general bilinear cells (Jacobian
+//                  per Gauss point, local mass matrix factorised per element).
 //   node phase     one CG2 node per lane: sum the forces of the <= 4 elements
 //                  around the node in ascending element order (deterministic,
 //                  no atomics), then the lumped-mass velocity update.
-// The per-element mass matrix and its inverse map are recomputed from the four
-// cell vertices in every subcycle (the paper's "on-the-fly map", Sec. 3.2)
-// instead of being stored: 64 B of vertices per element instead of a
-// n_s x n_G matrix.
+// The element maps are recomputed from the cell vertices in every subcycle
+// (the paper's "on-the-fly map", Sec. 3.2) instead of being stored.
 //
 // Arrays are element- or node-fastest (structure of arrays), so consecutive
 // lanes touch consecutive addresses for S, H, A, the forces and the node
@@ -25,11 +26,6 @@
 
 namespace mevp {
 namespace {
-
-template <class T>
-__device__ __forceinline__ T ld(const void *base, size_t i) {
-  return static_cast<const T *>(base)[i];
-}
 
 // Bilinear cell map from the vertices (0,0), (1,0), (0,1), (1,1) of the
 // reference square: J(xi, eta) = [[J00, J01], [J10, J11]] with
@@ -138,44 +134,228 @@ __device__ __forceinline__ double ice_strength(const KParams &p, const double (&
   return p.Pstar * h * exp(-p.C * (1.0 - a));
 }
 
+// VP stress at one Gauss point (Listing 1): Delta and P/Delta in double,
+// s11 = P/Delta (5/8 e11 + 3/8 e22) - P/2, s12 = P/Delta e12 / 4, s22 alike.
+template <class T>
+__device__ __forceinline__ void vp_stress(const KParams &p, double P, T e11, T e12, T e22, T &s11,
+                                          T &s12, T &s22) {
+  const double de11 = e11, de12 = e12, de22 = e22;
+  const double D2 = p.dmin2 + 1.25 * (de11 * de11 + de22 * de22) + 1.5 * de11 * de22 + de12 * de12;
+  const double PD = P / sqrt(D2);
+  const T tPD = T(PD), thP = T(0.5 * P);
+  s11 = tPD * (T(0.625) * e11 + T(0.375) * e22) - thP;
+  s12 = tPD * T(0.25) * e12;
+  s22 = tPD * (T(0.625) * e22 + T(0.375) * e11) - thP;
+}
+
+// Velocities of the 9 local nodes of element (ex, ey). In float they are
+// taken relative to local node 0 before narrowing (the gradient of a constant
+// is zero), which keeps the strain free of cancellation.
+template <class T>
+__device__ __forceinline__ void load_velocity(const DomDev &D, const double *v, int ex, int ey,
+                                              T (&vx)[9], T (&vy)[9]) {
+  const double *vxg = v + 2 * (size_t)D.node_off;
+  const double *vyg = vxg + D.nn;
+  const int NX = 2 * D.nx + 1;
+  const int j0 = 2 * ey * NX + 2 * ex;
+  double bx = 0.0, by = 0.0;
+  if (sizeof(T) < sizeof(double)) {
+    bx = vxg[j0];
+    by = vyg[j0];
+  }
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int j = j0 + b * NX + c;
+      vx[3 * b + c] = T(vxg[j] - bx);
+      vy[3 * b + c] = T(vyg[j] - by);
+    }
+}
+
+template <int NA>
+__device__ __forceinline__ void load_ice(const DevArrays &d, const DomDev &D, int el,
+                                         double (&Hc)[NA], double (&Ac)[NA]) {
+  const size_t ne = (size_t)D.ne;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    Hc[k] = d.H[((size_t)NA * D.elem_off) + k * ne + el];
+    Ac[k] = d.A[((size_t)NA * D.elem_off) + k * ne + el];
+  }
+}
+
+template <int NS, class T, class TS>
+__device__ __forceinline__ void relax_store(const DevArrays &d, const DomDev &D, int el,
+                                            const KParams &p, T (&R11)[NS], T (&R12)[NS],
+                                            T (&R22)[NS]) {
+  const size_t ne = (size_t)D.ne;
+  TS *S = static_cast<TS *>(d.S) + (size_t)3 * NS * D.elem_off;
+  const T fac = T(p.fac), ainv = T(p.ainv);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    R11[k] = fac * T(S[(0 * NS + k) * ne + el]) + ainv * R11[k];
+    R12[k] = fac * T(S[(1 * NS + k) * ne + el]) + ainv * R12[k];
+    R22[k] = fac * T(S[(2 * NS + k) * ne + el]) + ainv * R22[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    S[(0 * NS + k) * ne + el] = TS(R11[k]);
+    S[(1 * NS + k) * ne + el] = TS(R12[k]);
+    S[(2 * NS + k) * ne + el] = TS(R22[k]);
+  }
+}
+
+template <class T, class TS>
+__device__ __forceinline__ void store_forces(const DevArrays &d, const DomDev &D, int el,
+                                             const T (&fx)[9], const T (&fy)[9]) {
+  const size_t ne = (size_t)D.ne;
+  TS *fe = static_cast<TS *>(d.fe) + (size_t)18 * D.elem_off;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    fe[a * ne + el] = TS(fx[a]);
+    fe[(9 + a) * ne + el] = TS(fy[a]);
+  }
+}
+
 // ---------------------------------------------------------------------------
-// Element phase: strain -> stress update -> element nodal forces.
-//   T   type of the contractions (double, or float in mixed precision)
-//   TS  storage type of S and of the nodal forces
+// Element phase, parallelogram cells. J = [[J00, J01], [J10, J11]] is
+// constant, |J| cancels from the projections (M_e = |J| diag(int psi_k^2)), and
+//   w|J| grad v projected:  R11[k] = J11 (Axi vx)[k] - J10 (Aeta vx)[k], ...
+//   divergence:            f_x[a] = -(J11 (Axi^T S11)[a] - J01 (Axi^T S12)[a]
+//                                     + J00 (Aeta^T S12)[a] - J10 (Aeta^T S11)[a])
+// with the exact reference operators a_xi, a_eta of mevp_ref.hpp.
 // ---------------------------------------------------------------------------
 template <int NS, int NA, class T, class TS>
-__global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p) {
+__global__ void __launch_bounds__(kElemBlock) k_element_affine(DevArrays d, KParams p,
+                                                               const Blk *blks) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
-  const Blk blk = d.eblk[blockIdx.x];
+  const Blk blk = blks[blockIdx.x];
   const DomDev D = d.doms[blk.dom];
   const int el = blk.first + (int)threadIdx.x;
   if (el >= D.ne) return;
   const int ex = el % D.nx, ey = el / D.nx;
-  const size_t ne = (size_t)D.ne;
+
+  T J00, J01, J10, J11;
+  {
+    const double *VX = d.vert + 2 * (size_t)D.vert_off;
+    const double *VY = VX + D.nv;
+    const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
+    const double X0 = VX[i0], Y0 = VY[i0];
+    J00 = T(VX[i0 + 1] - X0);
+    J10 = T(VY[i0 + 1] - Y0);
+    J01 = T(VX[i2] - X0);
+    J11 = T(VY[i2] - Y0);
+  }
+  const T idet = T(1) / (J00 * J11 - J01 * J10);
+
+  // ---- strain ----
+  T vx[9], vy[9];
+  load_velocity<T>(D, d.v, ex, ey, vx, vy);
+  T E11[NS], E12[NS], E22[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    T gxx = 0, gxe = 0, gyx = 0, gye = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      if (a_xi(k, a) != 0.0) {
+        gxx += T(a_xi(k, a)) * vx[a];
+        gyx += T(a_xi(k, a)) * vy[a];
+      }
+      if (a_eta(k, a) != 0.0) {
+        gxe += T(a_eta(k, a)) * vx[a];
+        gye += T(a_eta(k, a)) * vy[a];
+      }
+    }
+    const T sc = idet * T(1.0 / dg_mass(k));
+    E11[k] = (J11 * gxx - J10 * gxe) * sc;
+    E22[k] = (J00 * gye - J01 * gyx) * sc;
+    E12[k] = T(0.5) * ((J00 * gxe - J01 * gxx) + (J11 * gyx - J10 * gye)) * sc;
+  }
+
+  // ---- stress update ----
+  double Hc[NA], Ac[NA];
+  load_ice<NA>(d, D, el, Hc, Ac);
+  const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
+  T R11[NS], R12[NS], R22[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    T e11 = 0, e12 = 0, e22 = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (Q::psi(k, q) != 0.0) {
+        const T ps = T(Q::psi(k, q));
+        e11 += E11[k] * ps;
+        e12 += E12[k] * ps;
+        e22 += E22[k] * ps;
+      }
+    }
+    const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
+    T s11, s12, s22;
+    vp_stress<T>(p, P, e11, e12, e22, s11, s12, s22);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (Q::psi(k, q) != 0.0) {
+        const T pw = T(Q::w(q) * Q::psi(k, q) / dg_mass(k));
+        R11[k] += pw * s11;
+        R12[k] += pw * s12;
+        R22[k] += pw * s22;
+      }
+    }
+  }
+  relax_store<NS, T, TS>(d, D, el, p, R11, R12, R22);
+
+  // ---- divergence, element part ----
+  T fx[9], fy[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    T bx11 = 0, be11 = 0, bx12 = 0, be12 = 0, bx22 = 0, be22 = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (a_xi(k, a) != 0.0) {
+        const T c = T(a_xi(k, a));
+        bx11 += c * R11[k];
+        bx12 += c * R12[k];
+        bx22 += c * R22[k];
+      }
+      if (a_eta(k, a) != 0.0) {
+        const T c = T(a_eta(k, a));
+        be11 += c * R11[k];
+        be12 += c * R12[k];
+        be22 += c * R22[k];
+      }
+    }
+    fx[a] = -((J11 * bx11 - J01 * bx12) + (J00 * be12 - J10 * be11));
+    fy[a] = -((J11 * bx12 - J01 * bx22) + (J00 * be22 - J10 * be12));
+  }
+  store_forces<T, TS>(d, D, el, fx, fy);
+}
+
+// ---------------------------------------------------------------------------
+// Element phase, general bilinear cells: strain -> stress update -> forces.
+//   T   type of the contractions (double, or float in mixed precision)
+//   TS  storage type of S and of the nodal forces
+// ---------------------------------------------------------------------------
+template <int NS, int NA, class T, class TS>
+__global__ void __launch_bounds__(kElemBlock) k_element_general(DevArrays d, KParams p,
+                                                                const Blk *blks) {
+  using Q = Quad<Ngp<NS>::value>;
+  constexpr int NG = Q::NG;
+  const Blk blk = blks[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int el = blk.first + (int)threadIdx.x;
+  if (el >= D.ne) return;
+  const int ex = el % D.nx, ey = el / D.nx;
 
   const Cell<T> cell = load_cell<T>(D, d.vert, ex, ey);
   Ldl<NS, T> mass;
   mass.template build<Q>(cell);
 
-  // ---- strain: gradients of the 9 nodal velocities (shifted by node 0 before
-  // narrowing; the gradient of a constant is zero) ----
-  const double *vxg = d.v + 2 * (size_t)D.node_off;
-  const double *vyg = vxg + D.nn;
-  const int NX = 2 * D.nx + 1;
-  const int j0 = 2 * ey * NX + 2 * ex;
+  // ---- strain ----
   T vx[9], vy[9];
-  {
-    const double bx = vxg[j0], by = vyg[j0];
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int j = j0 + b * NX + c;
-        vx[3 * b + c] = T(vxg[j] - bx);
-        vy[3 * b + c] = T(vyg[j] - by);
-      }
-  }
+  load_velocity<T>(D, d.v, ex, ey, vx, vy);
   T E11[NS], E12[NS], E22[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) E11[k] = E12[k] = E22[k] = T(0);
@@ -202,25 +382,21 @@ __global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p) 
     const T e12 = T(0.5) * w * ((J00 * gxe - J01 * gxx) + (J11 * gyx - J10 * gye));
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const T ps = T(Q::psi(k, q));
-      E11[k] += ps * e11;
-      E12[k] += ps * e12;
-      E22[k] += ps * e22;
+      if (Q::psi(k, q) != 0.0) {
+        const T ps = T(Q::psi(k, q));
+        E11[k] += ps * e11;
+        E12[k] += ps * e12;
+        E22[k] += ps * e22;
+      }
     }
   }
   mass.solve(E11);
   mass.solve(E12);
   mass.solve(E22);
 
-  // ---- stress update (Listing 1): Gauss values of E, ice strength, Delta,
-  // P/Delta, the VP stress, its projection and the relaxation ----
+  // ---- stress update ----
   double Hc[NA], Ac[NA];
-#pragma unroll
-  for (int k = 0; k < NA; ++k) {
-    Hc[k] = d.H[((size_t)NA * D.elem_off) + k * ne + el];
-    Ac[k] = d.A[((size_t)NA * D.elem_off) + k * ne + el];
-  }
-  // with one ice dof the strength is constant over the element: one exp per element
+  load_ice<NA>(d, D, el, Hc, Ac);
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
   T R11[NS], R12[NS], R22[NS];
 #pragma unroll
@@ -230,47 +406,33 @@ __global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p) 
     T e11 = 0, e12 = 0, e22 = 0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const T ps = T(Q::psi(k, q));
-      e11 += E11[k] * ps;
-      e12 += E12[k] * ps;
-      e22 += E22[k] * ps;
+      if (Q::psi(k, q) != 0.0) {
+        const T ps = T(Q::psi(k, q));
+        e11 += E11[k] * ps;
+        e12 += E12[k] * ps;
+        e22 += E22[k] * ps;
+      }
     }
     const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
-    const double de11 = e11, de12 = e12, de22 = e22;
-    const double D2 = p.dmin2 + 1.25 * (de11 * de11 + de22 * de22) + 1.5 * de11 * de22 + de12 * de12;
-    const double PD = P / sqrt(D2);
-    const T tPD = T(PD), thP = T(0.5 * P);
-    const T s11 = tPD * (T(0.625) * e11 + T(0.375) * e22) - thP;
-    const T s12 = tPD * T(0.25) * e12;
-    const T s22 = tPD * (T(0.625) * e22 + T(0.375) * e11) - thP;
+    T s11, s12, s22;
+    vp_stress<T>(p, P, e11, e12, e22, s11, s12, s22);
     T J00, J01, J10, J11;
     cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
     const T wd = T(Q::w(q)) * (J00 * J11 - J01 * J10);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const T pw = T(Q::psi(k, q)) * wd;
-      R11[k] += pw * s11;
-      R12[k] += pw * s12;
-      R22[k] += pw * s22;
+      if (Q::psi(k, q) != 0.0) {
+        const T pw = T(Q::psi(k, q)) * wd;
+        R11[k] += pw * s11;
+        R12[k] += pw * s12;
+        R22[k] += pw * s22;
+      }
     }
   }
   mass.solve(R11);
   mass.solve(R12);
   mass.solve(R22);
-  TS *S = static_cast<TS *>(d.S) + (size_t)3 * NS * D.elem_off;
-  const T fac = T(p.fac), ainv = T(p.ainv);
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    R11[k] = fac * T(S[(0 * NS + k) * ne + el]) + ainv * R11[k];
-    R12[k] = fac * T(S[(1 * NS + k) * ne + el]) + ainv * R12[k];
-    R22[k] = fac * T(S[(2 * NS + k) * ne + el]) + ainv * R22[k];
-  }
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    S[(0 * NS + k) * ne + el] = TS(R11[k]);
-    S[(1 * NS + k) * ne + el] = TS(R12[k]);
-    S[(2 * NS + k) * ne + el] = TS(R22[k]);
-  }
+  relax_store<NS, T, TS>(d, D, el, p, R11, R12, R22);
 
   // ---- divergence, element part: f[a] = -sum_q w_q |J_q| sigma(q) grad phi_a(q)
   //      = -sum_q (dphi_a/dxi Gxi + dphi_a/deta Geta) with G = w_q sigma adj(J)^T ----
@@ -282,10 +444,12 @@ __global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p) 
     T s11 = 0, s12 = 0, s22 = 0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-      const T ps = T(Q::psi(k, q));
-      s11 += R11[k] * ps;
-      s12 += R12[k] * ps;
-      s22 += R22[k] * ps;
+      if (Q::psi(k, q) != 0.0) {
+        const T ps = T(Q::psi(k, q));
+        s11 += R11[k] * ps;
+        s12 += R12[k] * ps;
+        s22 += R22[k] * ps;
+      }
     }
     T J00, J01, J10, J11;
     cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
@@ -306,16 +470,14 @@ __global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p) 
       }
     }
   }
-  TS *fe = static_cast<TS *>(d.fe) + (size_t)18 * D.elem_off;
-#pragma unroll
-  for (int a = 0; a < 9; ++a) {
-    fe[a * ne + el] = TS(fx[a]);
-    fe[(9 + a) * ne + el] = TS(fy[a]);
-  }
+  store_forces<T, TS>(d, D, el, fx, fy);
 }
 
 // ---------------------------------------------------------------------------
-// Node phase: deterministic gather of the element forces + velocity update.
+// Node phase: deterministic gather of the element forces + velocity update
+//   (c (1+beta) + d) v + b k x v = c beta v^{p-1} + g + d v_o + F
+// with c = M^H/dt, b = f M^H, d = m^A rho_o C_o |v_o - v^{p-1}| and
+// g = c v^n + m^A tau_a, solved in closed form; v = 0 on the boundary.
 // ---------------------------------------------------------------------------
 template <class TF>
 __global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p) {
@@ -351,30 +513,34 @@ __global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p) {
       Fy += (double)fe[(9 + a) * ne + e];
     }
   }
-  const size_t o = 2 * (size_t)D.node_off;
+  const double *nc = d.nc + (size_t)6 * D.node_off;
+  const size_t nn = (size_t)D.nn;
+  const double c = nc[j], ko = nc[nn + j], gx = nc[2 * nn + j], gy = nc[3 * nn + j];
+  const double ox = nc[4 * nn + j], oy = nc[5 * nn + j];
   const double ux = vx[j], uy = vy[j];
-  const double ox = d.ocean[o + j], oy = d.ocean[o + D.nn + j];
-  const double MH = d.MH[D.node_off + j], mA = d.mA[D.node_off + j];
-  const double c = MH * p.inv_dt;
   const double dox = ox - ux, doy = oy - uy;
-  const double dd = mA * p.rhoCo * sqrt(dox * dox + doy * doy);
-  const double bb = p.f_cor * MH;
-  const double rx = c * (p.beta * ux + d.vn[o + j]) + mA * d.tau[o + j] + dd * ox + Fx;
-  const double ry = c * (p.beta * uy + d.vn[o + D.nn + j]) + mA * d.tau[o + D.nn + j] + dd * oy + Fy;
+  const double dd = ko * sqrt(dox * dox + doy * doy);
+  const double bb = c * p.f_dt;
+  const double cb = c * p.beta;
+  const double rx = cb * ux + gx + dd * ox + Fx;
+  const double ry = cb * uy + gy + dd * oy + Fy;
   const double aa = c * (1.0 + p.beta) + dd;
   const double den = aa * aa + bb * bb;
   if (den == 0.0) {
     vx[j] = 0.0;
     vy[j] = 0.0;
   } else {
-    vx[j] = (aa * rx + bb * ry) / den;
-    vy[j] = (aa * ry - bb * rx) / den;
+    const double inv = 1.0 / den;
+    vx[j] = (aa * rx + bb * ry) * inv;
+    vy[j] = (aa * ry - bb * rx) * inv;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Start of a time step: v^n, lumped masses (gathered in ascending element
-// order from per-element integrals computed on the fly) and air stress.
+// Start of a time step: lumped masses gathered per node in ascending element
+// order from per-element integrals computed on the fly, air stress, and the
+// six node constants of the velocity update: c = M^H/dt, m^A rho_o C_o,
+// g = c v^n + m^A tau_a (2), ocean velocity (2).
 // ---------------------------------------------------------------------------
 template <int NS, int NA>
 __global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams p) {
@@ -386,12 +552,6 @@ __global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams 
   const int NX = 2 * D.nx + 1;
   const int ix = j % NX, iy = j / NX;
   const size_t o = 2 * (size_t)D.node_off;
-  d.vn[o + j] = d.v[o + j];
-  d.vn[o + D.nn + j] = d.v[o + D.nn + j];
-  const double wx = d.wind[o + j], wy = d.wind[o + D.nn + j];
-  const double sp = sqrt(wx * wx + wy * wy);
-  d.tau[o + j] = p.rhoCa * sp * wx;
-  d.tau[o + D.nn + j] = p.rhoCa * sp * wy;
 
   double MH = 0.0, mA = 0.0;
   const size_t ne = (size_t)D.ne;
@@ -442,8 +602,35 @@ __global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams 
       mA += sa;
     }
   }
-  d.MH[D.node_off + j] = MH;
-  d.mA[D.node_off + j] = mA;
+  const double wx = d.wind[o + j], wy = d.wind[o + D.nn + j];
+  const double sp = sqrt(wx * wx + wy * wy);
+  const double c = MH * p.inv_dt;
+  double *nc = d.nc + (size_t)6 * D.node_off;
+  const size_t nn = (size_t)D.nn;
+  nc[j] = c;
+  nc[nn + j] = mA * p.rhoCo;
+  nc[2 * nn + j] = c * d.v[o + j] + mA * (p.rhoCa * sp * wx);
+  nc[3 * nn + j] = c * d.v[o + D.nn + j] + mA * (p.rhoCa * sp * wy);
+  nc[4 * nn + j] = d.ocean[o + j];
+  nc[5 * nn + j] = d.ocean[o + D.nn + j];
+}
+
+// Per domain: 1 if every cell is a parallelogram (its edge vectors agree
+// exactly in double), 0 otherwise. The flag starts at 1; any lane that finds
+// a general cell stores 0.
+__global__ void __launch_bounds__(kElemBlock) k_cell_shape(DevArrays d, int dom, int *flag) {
+  const DomDev D = d.doms[dom];
+  for (int el = blockIdx.x * blockDim.x + threadIdx.x; el < D.ne; el += gridDim.x * blockDim.x) {
+    const int ex = el % D.nx, ey = el / D.nx;
+    const double *VX = d.vert + 2 * (size_t)D.vert_off;
+    const double *VY = VX + D.nv;
+    const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
+    const bool par = (VX[i0 + 1] - VX[i0] == VX[i2 + 1] - VX[i2]) &&
+                     (VY[i0 + 1] - VY[i0] == VY[i2 + 1] - VY[i2]) &&
+                     (VX[i2] - VX[i0] == VX[i2 + 1] - VX[i0 + 1]) &&
+                     (VY[i2] - VY[i0] == VY[i2 + 1] - VY[i0 + 1]);
+    if (!par) *flag = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -520,24 +707,38 @@ hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int 
 }
 
 template <int NS, int NA>
-static hipError_t element_t(const DevArrays &d, const KParams &p, bool mixed, int n_eblk,
-                            hipStream_t s) {
-  if (mixed)
-    hipLaunchKernelGGL((k_element<NS, NA, float, float>), dim3(n_eblk), dim3(kElemBlock), 0, s, d, p);
-  else
-    hipLaunchKernelGGL((k_element<NS, NA, double, double>), dim3(n_eblk), dim3(kElemBlock), 0, s, d, p);
+static hipError_t element_t(const DevArrays &d, const KParams &p, bool mixed, const Blk *blks,
+                            int n_aff, int n_gen, hipStream_t s) {
+  if (n_aff > 0) {
+    if (mixed)
+      hipLaunchKernelGGL((k_element_affine<NS, NA, float, float>), dim3(n_aff), dim3(kElemBlock), 0, s, d, p, blks);
+    else
+      hipLaunchKernelGGL((k_element_affine<NS, NA, double, double>), dim3(n_aff), dim3(kElemBlock), 0, s, d, p, blks);
+  }
+  if (n_gen > 0) {
+    if (mixed)
+      hipLaunchKernelGGL((k_element_general<NS, NA, float, float>), dim3(n_gen), dim3(kElemBlock), 0, s, d, p, blks + n_aff);
+    else
+      hipLaunchKernelGGL((k_element_general<NS, NA, double, double>), dim3(n_gen), dim3(kElemBlock), 0, s, d, p, blks + n_aff);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, int n_a, bool mixed,
-                                int n_eblk, hipStream_t s) {
+                                int n_aff, int n_gen, hipStream_t s) {
 #define MEVP_EL(NS_, NA_) \
-  if (n_s == NS_ && n_a == NA_) return element_t<NS_, NA_>(d, p, mixed, n_eblk, s);
+  if (n_s == NS_ && n_a == NA_) return element_t<NS_, NA_>(d, p, mixed, d.eblk, n_aff, n_gen, s);
   MEVP_EL(3, 1) MEVP_EL(3, 3) MEVP_EL(3, 6)
   MEVP_EL(6, 1) MEVP_EL(6, 3) MEVP_EL(6, 6)
   MEVP_EL(8, 1) MEVP_EL(8, 3) MEVP_EL(8, 6)
 #undef MEVP_EL
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_shape, dim3(grid_for((size_t)ne, kElemBlock)), dim3(kElemBlock), 0, s, d,
+                     dom, flag);
+  return hipGetLastError();
 }
 
 hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, int n_nblk,

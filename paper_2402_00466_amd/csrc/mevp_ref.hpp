@@ -87,3 +87,35 @@ struct Quad {
 };
 
 }  // namespace mevp
+
+namespace mevp {
+
+// ---------------------------------------------------------------------------
+// Exact element operators of a parallelogram (affine) cell.
+//
+// With a constant Jacobian the strain projection and the weak divergence are
+// constant matrices applied to the nodal velocities / DG coefficients, and
+// every DG and CG2 function is a product of 1D polynomials, so each entry is a
+// product of two exact 1D integrals over [0,1] (written with s = xi - 1/2):
+//   P0 = 1, P1 = s, P2 = s^2 - 1/12;  L0 = 2s^2 - s, L1 = 1 - 4s^2, L2 = 2s^2 + s
+//   I0[i][b] = int P_i L_b,   I1[i][c] = int P_i L_c'
+// (the Gauss rules of the general path integrate the same polynomials exactly).
+// ---------------------------------------------------------------------------
+constexpr double kI0[3][3] = {{1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0},
+                              {-1.0 / 12.0, 0.0, 1.0 / 12.0},
+                              {1.0 / 90.0, -1.0 / 45.0, 1.0 / 90.0}};
+constexpr double kI1[3][3] = {{-1.0, 0.0, 1.0},
+                              {1.0 / 3.0, -2.0 / 3.0, 1.0 / 3.0},
+                              {0.0, 0.0, 0.0}};
+constexpr double kNorm1D[3] = {1.0, 1.0 / 12.0, 1.0 / 180.0};
+// DG function k = P_kx(s) P_ky(t)
+constexpr int kDgX[8] = {0, 1, 0, 2, 1, 0, 2, 1};
+constexpr int kDgY[8] = {0, 0, 1, 0, 1, 2, 1, 2};
+
+// Axi[k][a] = int psi_k dphi_a/dxi, Aeta[k][a] = int psi_k dphi_a/deta over the
+// reference square (local node a = 3 b + c).
+constexpr double a_xi(int k, int a) { return kI1[kDgX[k]][a % 3] * kI0[kDgY[k]][a / 3]; }
+constexpr double a_eta(int k, int a) { return kI0[kDgX[k]][a % 3] * kI1[kDgY[k]][a / 3]; }
+constexpr double dg_mass(int k) { return kNorm1D[kDgX[k]] * kNorm1D[kDgY[k]]; }
+
+}  // namespace mevp
