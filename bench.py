@@ -6,9 +6,9 @@ kernel (v^n, lumped masses, air stress) and n_sub = 100 subcycles of strain,
 stress update, divergence and velocity update, with all inputs resident in HBM.
 Prints ONE JSON line:
   value         element-subcycles per second (elements x subcycles x steps / time)
-  roofline      the dominant kernel (element phase) against the HBM roofline,
-                from its average duration measured with HIP events on the
-                context's stream over the timed region
+  roofline      the dominant kernel (the fused subcycle kernel) against the
+                HBM roofline, from its average duration measured with HIP
+                events on the context's stream over the timed region
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
   variants      the same measurement for mixed precision, the larger meshes
                 and the 64-domain batch (one context, one launch per phase)
@@ -47,31 +47,35 @@ def kernel_hash() -> str:
 
 
 def alg_bytes(domains, precision):
-    """Algorithmic HBM bytes of one launch of each phase (what it must move if
-    nothing stays on chip between launches).
-      element phase: S read + write (2 x 3 n_s words), H and A (2 n_a doubles)
-                     per element; 2 doubles per vertex; v read, 2 doubles per node
-      node phase:    v read + write (4 doubles) and 8 doubles of per-node
-                     constants (v^n 2, ocean 2, air stress 2, M^H, m^A) per node
-    The element forces passed between the phases are implementation scratch and
-    not counted."""
+    """Algorithmic HBM bytes of one subcycle (what the method must move if
+    nothing stays on chip between subcycles), per the definition used
+    throughout: per element S read + write (2 x 3 n_s words of w_S bytes) and
+    H, A (2 n_a doubles); 16 B per vertex (on-the-fly geometry); per CG2 node
+    v read + write (32 B) and 8 doubles of per-step node data (v^n, ocean,
+    air stress, M^H, m^A: 64 B). Element forces, tiles' halo re-reads and the
+    like are implementation traffic and not counted.
+    Returns (subcycle bytes, element-phase share, node-phase share); the two
+    shares split the subcycle for the two-phase launch strategy (the element
+    phase also reads v: 16 B per node)."""
     ws = 4 if precision == "mixed" else 8
-    be = bn = 0
+    tot = be = bn = 0
     for d in domains:
         ne, nn, nv = d.nx * d.ny, (2 * d.nx + 1) * (2 * d.ny + 1), (d.nx + 1) * (d.ny + 1)
-        be += ne * (2 * 3 * d.n_s * ws + 2 * d.n_a * 8) + nv * 16 + nn * 16
-        bn += nn * (32 + 64)
-    return be, bn
+        per_e = ne * (2 * 3 * d.n_s * ws + 2 * d.n_a * 8) + nv * 16
+        tot += per_e + nn * 96
+        be += per_e + nn * 16
+        bn += nn * 96
+    return tot, be, bn
 
 
-def load_traffic(workload, precision):
-    """HBM traffic of the element phase from committed rocprofv3 PMC summaries,
-    if they were taken on the current kernel sources; else None."""
+def load_traffic(workload, precision, strategy):
+    """HBM traffic per launch of the dominant kernel from committed rocprofv3
+    PMC summaries, if they were taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(f"{workload}/{precision}")
+        rec = json.load(open(path)).get(f"{workload}/{precision}/{strategy}")
     except (ValueError, OSError):
         return None
     if not rec or rec.get("kernel_hash") != kernel_hash():
@@ -79,10 +83,11 @@ def load_traffic(workload, precision):
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(domains, precision, steps, warmup, n_sub):
+def run_gpu(domains, precision, steps, warmup, n_sub, strategy):
     import torch
     import paper_2402_00466_amd as M
-    ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in domains], precision=precision)
+    ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in domains], precision=precision,
+                    strategy=strategy)
     for k, d in enumerate(domains):
         ctx.upload(k, d)
     ctx.check_inputs()
@@ -109,28 +114,56 @@ def run_gpu(domains, precision, steps, warmup, n_sub):
     return ms, wall, tim
 
 
-def measure(domains, precision, steps, warmup, n_sub, workload):
-    ms, wall, tim = run_gpu(domains, precision, steps, warmup, n_sub)
+def measure(domains, precision, steps, warmup, n_sub, workload, strategy="fused"):
+    ms, wall, tim = run_gpu(domains, precision, steps, warmup, n_sub, strategy)
     el_sub = sum(d.nx * d.ny for d in domains) * n_sub * steps
     value = el_sub / (ms * 1e-3)
-    be, bn = alg_bytes(domains, precision)
-    ne_cnt, ne_ms = tim["element"]
-    nn_cnt, nn_ms = tim["node"]
-    el_avg = ne_ms / max(ne_cnt, 1)
-    nd_avg = nn_ms / max(nn_cnt, 1)
-    achieved = be / (el_avg * 1e-3) / 1e9
-    traffic = load_traffic(workload, precision)
+    tot, be, bn = alg_bytes(domains, precision)
+    c0, t0 = tim["element"]
+    c1, t1 = tim["node"]
+    k0 = t0 / max(c0, 1)
+    k1 = t1 / max(c1, 1)
+    if strategy == "fused":
+        kernel, kbytes, kms = "k_subcycle (fused subcycle)", tot, k0
+    else:
+        kernel, kbytes, kms = "k_element (element phase)", be, k0
+    achieved = kbytes / (kms * 1e-3) / 1e9
     return {
         "value": value, "ms_per_step": ms / steps, "wall_s": wall,
-        "kernels_ms": {"element_avg": el_avg, "node_avg": nd_avg,
+        "kernels_ms": {"subcycle_or_element_avg": k0, "node_avg": k1 if c1 else None,
                        "begin_step_avg": tim["begin_step"][1] / max(tim["begin_step"][0], 1),
-                       "element_launches": ne_cnt, "node_launches": nn_cnt},
-        "roofline": {"bound": "hbm", "kernel": "element_phase", "achieved": achieved,
+                       "launches": c0},
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "alg_bytes_per_launch": be,
-                     "node_phase_achieved": bn / (nd_avg * 1e-3) / 1e9,
-                     "subcycle_alg_GBs": (be + bn) / ((el_avg + nd_avg) * 1e-3) / 1e9},
+                     "traffic": load_traffic(workload, precision, strategy),
+                     "alg_bytes_per_launch": kbytes,
+                     "subcycle_alg_GBs": tot / ((k0 + k1) * 1e-3) / 1e9},
     }
+
+
+def traffic_probe(workload, precision, strategy, n_sub, copy_mib):
+    """A short run for hardware-counter collection (rocprofv3 --pmc): a device
+    copy of ``copy_mib`` MiB (reads and writes exactly that many bytes; the
+    calibration of the byte counters), then one start-of-step kernel and
+    ``n_sub`` subcycles of the workload."""
+    import torch
+    from synth_inputs import named_workload
+    import paper_2402_00466_amd as M
+    n = copy_mib * (1 << 20) // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    doms = named_workload(workload)
+    ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in doms], precision=precision,
+                    strategy=strategy)
+    for k, d in enumerate(doms):
+        ctx.upload(k, d)
+    ctx.step(n_sub)
+    ctx.sync()
+    log(f"probe done: copy {copy_mib} MiB x2, {workload} {precision} {strategy} {n_sub} subcycles")
 
 
 def cpu_baseline(domains, n_sub, budget_s):
@@ -163,9 +196,13 @@ def main():
     ap.add_argument("--n-sub", type=int, default=100)
     ap.add_argument("--workload", default="256x256-dg2")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--strategy", default="fused", choices=["fused", "two_phase"])
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the short counter-collection probe (see traffic_probe)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the mEVP subcycle "
@@ -180,35 +217,48 @@ def main():
     torch.cuda.set_device(0)
     import paper_2402_00466_amd as M
     M.lib()
+    if args.traffic_probe:
+        traffic_probe(args.workload, args.precision, args.strategy, args.n_sub if args.n_sub != 100 else 3,
+                      args.copy_mib)
+        return
 
     log(f"workload {args.workload} {args.precision}: generating inputs")
     doms = named_workload(args.workload)
-    head = measure(doms, args.precision, args.steps, args.warmup, args.n_sub, args.workload)
+    head = measure(doms, args.precision, args.steps, args.warmup, args.n_sub, args.workload,
+                   args.strategy)
     log(f"headline {head['value']:.3e} element-subcycles/s, {head['ms_per_step']:.3f} ms/step")
 
     variants = {}
     if not args.no_variants:
-        plan = [(args.workload, "mixed" if args.precision == "fp64" else "fp64", args.steps),
-                ("1024x1024-dg2", "fp64", 3), ("1024x1024-dg2", "mixed", 3),
-                ("2048x2048-dg2", "fp64", 2), ("2048x2048-dg2", "mixed", 2),
-                ("batch64-dg2", "fp64", 2), ("batch64-dg2", "mixed", 2)]
-        for wl, prec, st in plan:
-            log(f"variant {wl} {prec} ({st} steps)")
+        other = "mixed" if args.precision == "fp64" else "fp64"
+        plan = [(args.workload, other, args.steps, args.strategy),
+                (args.workload, args.precision, args.steps, "two_phase"),
+                ("1024x1024-dg2", "fp64", 3, "fused"), ("1024x1024-dg2", "mixed", 3, "fused"),
+                ("2048x2048-dg2", "fp64", 2, "fused"), ("2048x2048-dg2", "mixed", 2, "fused"),
+                ("2048x2048-dg2", "fp64", 2, "two_phase"),
+                ("batch64-dg2", "fp64", 2, "fused"), ("batch64-dg2", "mixed", 2, "fused")]
+        for wl, prec, st, strat in plan:
+            log(f"variant {wl} {prec} {strat} ({st} steps)")
             ds = doms if wl == args.workload else named_workload(wl)
-            r = measure(ds, prec, st, 1, args.n_sub, wl)
-            variants[f"{wl}/{prec}"] = {
+            r = measure(ds, prec, st, 1, args.n_sub, wl, strat)
+            variants[f"{wl}/{prec}/{strat}"] = {
                 "value": r["value"], "ms_per_step": r["ms_per_step"], "steps": st,
                 "elements": sum(d.nx * d.ny for d in ds),
-                "element_phase_ms": r["kernels_ms"]["element_avg"],
+                "kernel_ms": r["kernels_ms"]["subcycle_or_element_avg"],
                 "node_phase_ms": r["kernels_ms"]["node_avg"],
                 "roofline_frac": r["roofline"]["frac"],
                 "achieved_GBs": r["roofline"]["achieved"],
                 "subcycle_alg_GBs": r["roofline"]["subcycle_alg_GBs"]}
-            log(f"  {r['value']:.3e} element-subcycles/s, element phase {r['roofline']['frac']:.3f} of HBM peak")
+            log(f"  {r['value']:.3e} element-subcycles/s, {r['roofline']['kernel']} at "
+                f"{r['roofline']['frac']:.3f} of HBM peak")
             del ds
-        f64 = variants.get(f"{args.workload}/mixed")
-        if f64 and args.precision == "fp64":
-            variants["mixed_speedup_over_fp64"] = f64["value"] / head["value"]
+        mix = variants.get(f"{args.workload}/mixed/{args.strategy}")
+        if mix and args.precision == "fp64":
+            variants["mixed_speedup_over_fp64"] = mix["value"] / head["value"]
+        for wl in ("2048x2048-dg2", "batch64-dg2"):
+            a, b = variants.get(f"{wl}/mixed/fused"), variants.get(f"{wl}/fp64/fused")
+            if a and b:
+                variants[f"{wl}/mixed_speedup_over_fp64"] = a["value"] / b["value"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -230,6 +280,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "precision": args.precision,
+                   "strategy": args.strategy,
                    "domains": len(doms), "elements": sum(d.nx * d.ny for d in doms),
                    "mesh": f"{d0.nx}x{d0.ny}", "n_s": d0.n_s, "n_a": d0.n_a,
                    "n_sub": args.n_sub, "step": "one mEVP time step (start-of-step kernel + n_sub subcycles)"},

@@ -92,6 +92,19 @@ typedef struct {
   int nx, ny, n_s, n_a;
 } mevp_domain_desc;
 
+/* How a subcycle is mapped to launches (both compute the same values; the
+ * nodal force sums are taken in the same order, so results agree bitwise).
+ * FUSED (default): one launch per subcycle; a workgroup owns a tile of
+ * elements and the CG2 nodes at its low edges, recomputes the forces of a
+ * one-element halo, keeps all element forces in LDS and updates its nodes;
+ * v and S are double-buffered in the workspace.
+ * TWO_PHASE: an element launch writing the element forces to the workspace,
+ * then a node launch gathering them. */
+typedef enum {
+  MEVP_STRATEGY_FUSED = 0,
+  MEVP_STRATEGY_TWO_PHASE = 1
+} mevp_strategy;
+
 typedef struct mevp_ctx mevp_ctx;
 
 /* Fill *out with the default parameters. EINVAL if out is NULL. */
@@ -114,6 +127,9 @@ mevp_status mevp_workspace_size(const mevp_domain_desc *domains, int n_domains,
 mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
                         const mevp_domain_desc *domains, int n_domains, void *workspace,
                         size_t ws_bytes, void *hip_stream, mevp_ctx **out);
+
+/* Select how subcycles are launched (default MEVP_STRATEGY_FUSED). */
+mevp_status mevp_set_strategy(mevp_ctx *ctx, mevp_strategy strategy);
 
 /* Replace the parameters (validated as in mevp_create). */
 mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params);

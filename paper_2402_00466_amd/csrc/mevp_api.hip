@@ -25,8 +25,13 @@ struct mevp_ctx {
   std::vector<mevp_domain_desc> desc;
   std::vector<DomDev> dom_h;
   std::vector<Blk> eblk_h, nblk_h;
+  std::vector<Tile> tiles_h;
   std::vector<unsigned char> affine;  // per domain: every cell a parallelogram
-  int n_aff = 0;                      // leading element blocks of affine domains
+  Launch eblk_split{0, 0};            // element blocks: parallelogram domains, then the rest
+  Launch tile_split{0, 0};            // tiles likewise
+  Tile *tiles_d = nullptr;
+  int cur = 0;                        // which of the two v / S buffers holds the state
+  mevp_strategy strategy = MEVP_STRATEGY_FUSED;
   DevArrays d{};
   DomDev *doms_d = nullptr;
   Blk *eblk_d = nullptr, *nblk_d = nullptr;
@@ -85,7 +90,7 @@ KParams derive(const mevp_params &p) {
 
 // Layout of the workspace: offsets in bytes of every array.
 struct Layout {
-  size_t doms, eblk, nblk, flag, vert, H, A, wind, ocean, v, nc, S, fe, total;
+  size_t doms, eblk, nblk, tiles, flag, vert, H, A, wind, ocean, v, nc, S, fe, total;
   size_t tot_e, tot_n, tot_v;
   int n_eblk, n_nblk;
   int ns, na;
@@ -96,7 +101,7 @@ mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout
   if (prec != MEVP_FP64 && prec != MEVP_MIXED) return MEVP_EINVAL;
   const int ns = dd[0].n_s, na = dd[0].n_a;
   if (!(ns == 3 || ns == 6 || ns == 8) || !(na == 1 || na == 3 || na == 6)) return MEVP_EINVAL;
-  long long te = 0, tn = 0, tv = 0, neb = 0, nnb = 0;
+  long long te = 0, tn = 0, tv = 0, neb = 0, nnb = 0, ntl = 0;
   for (int i = 0; i < nd; ++i) {
     const mevp_domain_desc &d = dd[i];
     if (d.n_s != ns || d.n_a != na) return MEVP_EINVAL;
@@ -109,6 +114,7 @@ mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout
     tv += v;
     neb += (e + kElemBlock - 1) / kElemBlock;
     nnb += (n + kNodeBlock - 1) / kNodeBlock;
+    ntl += (long long)((d.nx + kTileEX - 2) / (kTileEX - 1)) * ((d.ny + kTileEY - 2) / (kTileEY - 1));
     if (te > kIndexMax || tn > kIndexMax || 2 * tn > kIndexMax || 18 * te > (1LL << 40))
       return MEVP_EINVAL;
   }
@@ -122,15 +128,16 @@ mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout
   L->doms = take(sizeof(DomDev) * nd);
   L->eblk = take(sizeof(Blk) * neb);
   L->nblk = take(sizeof(Blk) * nnb);
+  L->tiles = take(sizeof(Tile) * ntl);
   L->flag = take(sizeof(int) * 4);
   L->vert = take(sizeof(double) * 2 * tv);
   L->H = take(sizeof(double) * na * te);
   L->A = take(sizeof(double) * na * te);
   L->wind = take(sizeof(double) * 2 * tn);
   L->ocean = take(sizeof(double) * 2 * tn);
-  L->v = take(sizeof(double) * 2 * tn);
+  L->v = take(sizeof(double) * 4 * tn);
   L->nc = take(sizeof(double) * 6 * tn);
-  L->S = take(ws * 3 * ns * te);
+  L->S = take(ws * 6 * ns * te);
   L->fe = take(ws * 18 * te);
   L->total = off;
   L->tot_e = (size_t)te;
@@ -176,17 +183,52 @@ void timer_stop(mevp_ctx *c, int ph, int slot) {
   if (hipEventRecord(t.ev[2 * slot + 1], c->stream) == hipSuccess) t.used = slot + 1;
 }
 
-// Element blocks with the domains of parallelogram cells first (one launch of
-// the affine kernel), then the rest (one launch of the general kernel).
+// Element blocks and fused-kernel tiles with the domains of parallelogram
+// cells first (one launch of the constant-Jacobian kernel), then the rest
+// (one launch of the general kernel).
 void order_blocks(mevp_ctx *c) {
   c->eblk_h.clear();
+  c->tiles_h.clear();
+  constexpr int TX = kTileEX - 1, TY = kTileEY - 1;
   for (int pass = 0; pass < 2; ++pass) {
     for (int i = 0; i < c->nd; ++i) {
       if ((pass == 0) != (c->affine[i] != 0)) continue;
-      for (int f = 0; f < c->dom_h[i].ne; f += kElemBlock) c->eblk_h.push_back(Blk{i, f});
+      const DomDev &D = c->dom_h[i];
+      for (int f = 0; f < D.ne; f += kElemBlock) c->eblk_h.push_back(Blk{i, f});
+      for (int y0 = 0; y0 < D.ny; y0 += TY)
+        for (int x0 = 0; x0 < D.nx; x0 += TX) c->tiles_h.push_back(Tile{i, x0, y0, 0});
     }
-    if (pass == 0) c->n_aff = (int)c->eblk_h.size();
+    if (pass == 0) {
+      c->eblk_split.n_aff = (int)c->eblk_h.size();
+      c->tile_split.n_aff = (int)c->tiles_h.size();
+    }
   }
+  c->eblk_split.n_gen = (int)c->eblk_h.size() - c->eblk_split.n_aff;
+  c->tile_split.n_gen = (int)c->tiles_h.size() - c->tile_split.n_aff;
+  // Workgroup i of a launch runs on XCD i % 8. Permute each launch's tiles so
+  // that every XCD gets one contiguous band of tiles: neighbouring tiles share
+  // halo elements and cache lines, which then meet in the same L2.
+  auto xcd_order = [](Tile *t, int n) {
+    std::vector<Tile> src(t, t + n);
+    int start = 0;
+    for (int x = 0; x < kNumXcd; ++x) {
+      const int cnt = (n - x + kNumXcd - 1) / kNumXcd;  // workgroups x, x+8, ...
+      for (int s = 0; s < cnt; ++s) t[x + s * kNumXcd] = src[start + s];
+      start += cnt;
+    }
+  };
+  xcd_order(c->tiles_h.data(), c->tile_split.n_aff);
+  xcd_order(c->tiles_h.data() + c->tile_split.n_aff, c->tile_split.n_gen);
+}
+
+size_t s_words(const mevp_ctx *c) { return (size_t)3 * c->ns * c->tot_e; }
+size_t s_bytes(const mevp_ctx *c) {
+  return (c->prec == MEVP_MIXED ? sizeof(float) : sizeof(double));
+}
+// current / other state buffers
+double *v_buf(mevp_ctx *c, int which) { return c->d.v + (size_t)which * 2 * c->tot_n; }
+void *S_buf(mevp_ctx *c, int which) {
+  return static_cast<char *>(c->d.S) + (size_t)which * s_words(c) * s_bytes(c);
 }
 
 }  // namespace
@@ -298,10 +340,12 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
   c->doms_d = reinterpret_cast<DomDev *>(base + L.doms);
   c->eblk_d = reinterpret_cast<Blk *>(base + L.eblk);
   c->nblk_d = reinterpret_cast<Blk *>(base + L.nblk);
+  c->tiles_d = reinterpret_cast<Tile *>(base + L.tiles);
   DevArrays &d = c->d;
   d.doms = c->doms_d;
   d.eblk = c->eblk_d;
   d.nblk = c->nblk_d;
+  d.tiles = c->tiles_d;
   d.flag = reinterpret_cast<int *>(base + L.flag);
   d.vert = reinterpret_cast<double *>(base + L.vert);
   d.H = reinterpret_cast<double *>(base + L.H);
@@ -317,6 +361,7 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
   mevp_status rc = copy(c->doms_d, c->dom_h.data(), sizeof(DomDev) * n_domains, s);
   if (rc == MEVP_OK) rc = copy(c->eblk_d, c->eblk_h.data(), sizeof(Blk) * c->eblk_h.size(), s);
   if (rc == MEVP_OK) rc = copy(c->nblk_d, c->nblk_h.data(), sizeof(Blk) * c->nblk_h.size(), s);
+  if (rc == MEVP_OK) rc = copy(c->tiles_d, c->tiles_h.data(), sizeof(Tile) * c->tiles_h.size(), s);
   // zero everything after the tables: fields, state, scratch
   if (rc == MEVP_OK)
     rc = hip_status(launch_fill(base + L.flag, (L.total - L.flag) / 4, 0u, s));
@@ -357,6 +402,7 @@ mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy) {
     ctx->affine[dom] = aff != 0;
     order_blocks(ctx);
     st = copy(ctx->eblk_d, ctx->eblk_h.data(), sizeof(Blk) * ctx->eblk_h.size(), s);
+    if (st == MEVP_OK) st = copy(ctx->tiles_d, ctx->tiles_h.data(), sizeof(Tile) * ctx->tiles_h.size(), s);
     if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(s));
     if (st != MEVP_OK) return st;
   }
@@ -393,36 +439,42 @@ mevp_status mevp_set_forcing(mevp_ctx *ctx, int dom, const double *wind_xy,
 mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const double *S) {
   if (bad_dom(ctx, dom) || !v_xy || !S) return MEVP_EINVAL;
   const DomDev &D = ctx->dom_h[dom];
-  mevp_status st = copy(ctx->d.v + 2 * (size_t)D.node_off, v_xy, sizeof(double) * 2 * D.nn,
-                        ctx->stream);
-  if (st != MEVP_OK) return st;
   const size_t n = (size_t)3 * ctx->ns * D.ne, o = (size_t)3 * ctx->ns * D.elem_off;
-  if (ctx->prec == MEVP_FP64) return copy(static_cast<double *>(ctx->d.S) + o, S, sizeof(double) * n, ctx->stream);
-  hipPointerAttribute_t attr;
-  if (hipPointerGetAttributes(&attr, S) != hipSuccess || attr.type != hipMemoryTypeDevice) {
-    (void)hipGetLastError();
-    return MEVP_EINVAL;  // the rounding to float runs on the device: S must be device memory
+  if (ctx->prec == MEVP_MIXED) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, S) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      return MEVP_EINVAL;  // the rounding to float runs on the device: S must be device memory
+    }
   }
-  return hip_status(launch_convert_d2f(S, static_cast<float *>(ctx->d.S) + o, n, ctx->stream));
+  mevp_status st = copy(v_buf(ctx, ctx->cur) + 2 * (size_t)D.node_off, v_xy,
+                        sizeof(double) * 2 * D.nn, ctx->stream);
+  if (st != MEVP_OK) return st;
+  if (ctx->prec == MEVP_FP64)
+    return copy(static_cast<double *>(S_buf(ctx, ctx->cur)) + o, S, sizeof(double) * n, ctx->stream);
+  return hip_status(launch_convert_d2f(S, static_cast<float *>(S_buf(ctx, ctx->cur)) + o, n, ctx->stream));
 }
 
 mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S) {
   if (bad_dom(ctx, dom)) return MEVP_EINVAL;
   const DomDev &D = ctx->dom_h[dom];
-  if (v_xy) {
-    mevp_status st = copy(v_xy, ctx->d.v + 2 * (size_t)D.node_off, sizeof(double) * 2 * D.nn,
-                          ctx->stream);
-    if (st != MEVP_OK) return st;
-  }
-  if (S) {
-    const size_t n = (size_t)3 * ctx->ns * D.ne, o = (size_t)3 * ctx->ns * D.elem_off;
-    if (ctx->prec == MEVP_FP64) return copy(S, static_cast<double *>(ctx->d.S) + o, sizeof(double) * n, ctx->stream);
+  if (S && ctx->prec == MEVP_MIXED) {
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, S) != hipSuccess || attr.type != hipMemoryTypeDevice) {
       (void)hipGetLastError();
       return MEVP_EINVAL;
     }
-    return hip_status(launch_convert_f2d(static_cast<const float *>(ctx->d.S) + o, S, n, ctx->stream));
+  }
+  if (v_xy) {
+    mevp_status st = copy(v_xy, v_buf(ctx, ctx->cur) + 2 * (size_t)D.node_off,
+                          sizeof(double) * 2 * D.nn, ctx->stream);
+    if (st != MEVP_OK) return st;
+  }
+  if (S) {
+    const size_t n = (size_t)3 * ctx->ns * D.ne, o = (size_t)3 * ctx->ns * D.elem_off;
+    if (ctx->prec == MEVP_FP64)
+      return copy(S, static_cast<const double *>(S_buf(ctx, ctx->cur)) + o, sizeof(double) * n, ctx->stream);
+    return hip_status(launch_convert_f2d(static_cast<const float *>(S_buf(ctx, ctx->cur)) + o, S, n, ctx->stream));
   }
   return MEVP_OK;
 }
@@ -433,7 +485,8 @@ mevp_status mevp_begin_step(mevp_ctx *ctx) {
     if (!ctx->geo_set[i] || !ctx->fld_set[i] || !ctx->frc_set[i]) return MEVP_ESTATE;
   const int slot = timer_start(ctx, 2);
   mevp_status st = hip_status(launch_begin_step(ctx->d, ctx->kp, ctx->na, ctx->ns,
-                                                (int)ctx->nblk_h.size(), ctx->stream));
+                                                v_buf(ctx, ctx->cur), (int)ctx->nblk_h.size(),
+                                                ctx->stream));
   timer_stop(ctx, 2, slot);
   return st;
 }
@@ -444,17 +497,37 @@ mevp_status mevp_subcycles(mevp_ctx *ctx, int n) {
     if (!ctx->geo_set[i] || !ctx->fld_set[i] || !ctx->frc_set[i]) return MEVP_ESTATE;
   const bool mixed = ctx->prec == MEVP_MIXED;
   for (int it = 0; it < n; ++it) {
-    int slot = timer_start(ctx, 0);
-    hipError_t e = launch_element_phase(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->n_aff,
-                                        (int)ctx->eblk_h.size() - ctx->n_aff, ctx->stream);
-    timer_stop(ctx, 0, slot);
-    if (e == hipSuccess) {
-      slot = timer_start(ctx, 1);
-      e = launch_node_phase(ctx->d, ctx->kp, mixed, (int)ctx->nblk_h.size(), ctx->stream);
-      timer_stop(ctx, 1, slot);
+    hipError_t e;
+    if (ctx->strategy == MEVP_STRATEGY_FUSED) {
+      const int nxt = ctx->cur ^ 1;
+      const Bufs b{v_buf(ctx, ctx->cur), v_buf(ctx, nxt), S_buf(ctx, ctx->cur), S_buf(ctx, nxt)};
+      const int slot = timer_start(ctx, 0);
+      e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->tile_split, b,
+                                ctx->stream);
+      timer_stop(ctx, 0, slot);
+      if (e == hipSuccess) ctx->cur = nxt;
+    } else {
+      const Bufs b{v_buf(ctx, ctx->cur), v_buf(ctx, ctx->cur), S_buf(ctx, ctx->cur),
+                   S_buf(ctx, ctx->cur)};
+      int slot = timer_start(ctx, 0);
+      e = launch_element_phase(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->eblk_split, b,
+                               ctx->stream);
+      timer_stop(ctx, 0, slot);
+      if (e == hipSuccess) {
+        slot = timer_start(ctx, 1);
+        e = launch_node_phase(ctx->d, ctx->kp, mixed, (int)ctx->nblk_h.size(), b, ctx->stream);
+        timer_stop(ctx, 1, slot);
+      }
     }
     if (e != hipSuccess) return MEVP_EDEVICE;
   }
+  return MEVP_OK;
+}
+
+mevp_status mevp_set_strategy(mevp_ctx *ctx, mevp_strategy strategy) {
+  if (!ctx || (strategy != MEVP_STRATEGY_FUSED && strategy != MEVP_STRATEGY_TWO_PHASE))
+    return MEVP_EINVAL;
+  ctx->strategy = strategy;
   return MEVP_OK;
 }
 
@@ -499,12 +572,12 @@ mevp_status mevp_check_state(mevp_ctx *ctx) {
   hipStream_t s = ctx->stream;
   mevp_status st = hip_status(launch_fill(ctx->d.flag, 1, 0u, s));
   const size_t nS = (size_t)3 * ctx->ns * ctx->tot_e;
-  if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.v, 2 * ctx->tot_n, ctx->d.flag, 1, s));
+  if (st == MEVP_OK) st = hip_status(launch_check_finite(v_buf(ctx, ctx->cur), 2 * ctx->tot_n, ctx->d.flag, 1, s));
   if (st == MEVP_OK) {
     if (ctx->prec == MEVP_FP64)
-      st = hip_status(launch_check_finite(static_cast<const double *>(ctx->d.S), nS, ctx->d.flag, 1, s));
+      st = hip_status(launch_check_finite(static_cast<const double *>(S_buf(ctx, ctx->cur)), nS, ctx->d.flag, 1, s));
     else
-      st = hip_status(launch_check_finite_f(static_cast<const float *>(ctx->d.S), nS, ctx->d.flag, 1, s));
+      st = hip_status(launch_check_finite_f(static_cast<const float *>(S_buf(ctx, ctx->cur)), nS, ctx->d.flag, 1, s));
   }
   int flag = 0;
   if (st == MEVP_OK) st = read_flag(ctx, &flag);

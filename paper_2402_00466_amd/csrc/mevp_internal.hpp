@@ -24,6 +24,27 @@ struct Blk {
   int first;
 };
 
+// A tile of the fused subcycle kernel: domain and the first owned element.
+struct Tile {
+  int dom;
+  int x0, y0;
+  int pad;
+};
+
+// Buffers one subcycle reads and writes (context-wide bases; the fused kernel
+// double-buffers v and S, the two-phase kernels update them in place).
+struct Bufs {
+  const double *v_in;
+  double *v_out;
+  const void *S_in;
+  void *S_out;
+};
+
+// Leading blocks (or tiles) of parallelogram-cell domains, then the rest.
+struct Launch {
+  int n_aff, n_gen;
+};
+
 // Scalars the kernels need, derived once from mevp_params on the host.
 struct KParams {
   double Pstar, C, dmin2;  // P*, concentration factor, Delta_min^2
@@ -37,29 +58,39 @@ struct DevArrays {
   const DomDev *doms;
   const Blk *eblk;  // element blocks: parallelogram-cell domains first, then general
   const Blk *nblk;  // node blocks
+  const Tile *tiles;  // fused-kernel tiles: parallelogram-cell domains first
   const double *vert;  // [dom][2][nv]
   const double *H;     // [dom][n_a][ne]
   const double *A;
   const double *wind;  // [dom][2][nn]
   const double *ocean;
-  double *v;           // [dom][2][nn]
+  double *v;           // [dom][2][nn] (two buffers: v and v + 2 * total nodes)
   double *nc;          // [dom][6][nn] node constants of the velocity update
-  void *S;             // [dom][3][n_s][ne], double or float
+  void *S;             // [dom][3][n_s][ne], double or float (two buffers)
   void *fe;            // [dom][18][ne] element nodal forces, double or float
   int *flag;           // check results
 };
 
 constexpr int kElemBlock = 256;
 constexpr int kNodeBlock = 256;
+// fused kernel: a 17 x 15 element tile per workgroup, 16 x 14 of them owned
+// (16 owned elements = one 128-byte line of a double array per row)
+constexpr int kTileEX = 17;
+constexpr int kTileEY = 15;
+constexpr int kTileThreads = kTileEX * kTileEY;
+// workgroups are dealt to the 8 XCDs of the chip in turn
+constexpr int kNumXcd = 8;
 
 // Launchers (mevp_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int n_s,
-                             int n_nblk, hipStream_t s);
+                             const double *v, int n_nblk, hipStream_t s);
 hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, int n_a,
-                                bool mixed, int n_aff, int n_gen, hipStream_t s);
-hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s);
-hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, int n_nblk,
+                                bool mixed, const Launch &L, Bufs b, hipStream_t s);
+hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, int n_nblk, Bufs b,
                              hipStream_t s);
+hipError_t launch_fused_subcycle(const DevArrays &d, const KParams &p, int n_s, int n_a,
+                                 bool mixed, const Launch &L, Bufs b, hipStream_t s);
+hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s);
 hipError_t launch_fill(void *dst, size_t n_words32, uint32_t value, hipStream_t s);
 hipError_t launch_convert_d2f(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_convert_f2d(const float *src, double *dst, size_t n, hipStream_t s);

@@ -184,58 +184,63 @@ __device__ __forceinline__ void load_ice(const DevArrays &d, const DomDev &D, in
   }
 }
 
+// Relaxation of Listing 1: R <- fac S_in + ainv R (R holds Pi_e(s) on entry).
 template <int NS, class T, class TS>
-__device__ __forceinline__ void relax_store(const DevArrays &d, const DomDev &D, int el,
-                                            const KParams &p, T (&R11)[NS], T (&R12)[NS],
-                                            T (&R22)[NS]) {
-  const size_t ne = (size_t)D.ne;
-  TS *S = static_cast<TS *>(d.S) + (size_t)3 * NS * D.elem_off;
+__device__ __forceinline__ void relax(const TS *S_in, size_t ne, int el, const KParams &p,
+                                      T (&R11)[NS], T (&R12)[NS], T (&R22)[NS]) {
   const T fac = T(p.fac), ainv = T(p.ainv);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    R11[k] = fac * T(S[(0 * NS + k) * ne + el]) + ainv * R11[k];
-    R12[k] = fac * T(S[(1 * NS + k) * ne + el]) + ainv * R12[k];
-    R22[k] = fac * T(S[(2 * NS + k) * ne + el]) + ainv * R22[k];
+    R11[k] = fac * T(S_in[(0 * NS + k) * ne + el]) + ainv * R11[k];
+    R12[k] = fac * T(S_in[(1 * NS + k) * ne + el]) + ainv * R12[k];
+    R22[k] = fac * T(S_in[(2 * NS + k) * ne + el]) + ainv * R22[k];
   }
+}
+
+template <int NS, class T, class TS>
+__device__ __forceinline__ void store_stress(TS *S_out, size_t ne, int el, const T (&R11)[NS],
+                                             const T (&R12)[NS], const T (&R22)[NS]) {
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    S[(0 * NS + k) * ne + el] = TS(R11[k]);
-    S[(1 * NS + k) * ne + el] = TS(R12[k]);
-    S[(2 * NS + k) * ne + el] = TS(R22[k]);
+    S_out[(0 * NS + k) * ne + el] = TS(R11[k]);
+    S_out[(1 * NS + k) * ne + el] = TS(R12[k]);
+    S_out[(2 * NS + k) * ne + el] = TS(R22[k]);
   }
 }
 
-template <class T, class TS>
-__device__ __forceinline__ void store_forces(const DevArrays &d, const DomDev &D, int el,
-                                             const T (&fx)[9], const T (&fy)[9]) {
-  const size_t ne = (size_t)D.ne;
-  TS *fe = static_cast<TS *>(d.fe) + (size_t)18 * D.elem_off;
-#pragma unroll
-  for (int a = 0; a < 9; ++a) {
-    fe[a * ne + el] = TS(fx[a]);
-    fe[(9 + a) * ne + el] = TS(fy[a]);
+// Per-domain base pointers of the buffers a subcycle reads and writes.
+template <class TS>
+struct DomBufs {
+  const double *v_in;
+  double *v_out;
+  const TS *S_in;
+  TS *S_out;
+  __device__ __forceinline__ DomBufs(const Bufs &b, const DomDev &D, int ns) {
+    v_in = b.v_in + 2 * (size_t)D.node_off;
+    v_out = b.v_out + 2 * (size_t)D.node_off;
+    S_in = static_cast<const TS *>(b.S_in) + (size_t)3 * ns * D.elem_off;
+    S_out = static_cast<TS *>(b.S_out) + (size_t)3 * ns * D.elem_off;
   }
-}
+};
 
 // ---------------------------------------------------------------------------
-// Element phase, parallelogram cells. J = [[J00, J01], [J10, J11]] is
-// constant, |J| cancels from the projections (M_e = |J| diag(int psi_k^2)), and
+// Element update, parallelogram cells: strain -> stress update -> nodal forces.
+// J = [[J00, J01], [J10, J11]] is constant, |J| cancels from the projections
+// (M_e = |J| diag(int psi_k^2)), and
 //   w|J| grad v projected:  R11[k] = J11 (Axi vx)[k] - J10 (Aeta vx)[k], ...
 //   divergence:            f_x[a] = -(J11 (Axi^T S11)[a] - J01 (Axi^T S12)[a]
 //                                     + J00 (Aeta^T S12)[a] - J10 (Aeta^T S11)[a])
 // with the exact reference operators a_xi, a_eta of mevp_ref.hpp.
+// On return R holds the new stress coefficients and fx, fy the forces.
 // ---------------------------------------------------------------------------
 template <int NS, int NA, class T, class TS>
-__global__ void __launch_bounds__(kElemBlock) k_element_affine(DevArrays d, KParams p,
-                                                               const Blk *blks) {
+__device__ __forceinline__ void element_affine(const DevArrays &d, const DomDev &D,
+                                               const KParams &p, const double *v_in,
+                                               const TS *S_in, int el, int ex, int ey,
+                                               T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
+                                               T (&fx)[9], T (&fy)[9]) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
-  const Blk blk = blks[blockIdx.x];
-  const DomDev D = d.doms[blk.dom];
-  const int el = blk.first + (int)threadIdx.x;
-  if (el >= D.ne) return;
-  const int ex = el % D.nx, ey = el / D.nx;
-
   T J00, J01, J10, J11;
   {
     const double *VX = d.vert + 2 * (size_t)D.vert_off;
@@ -251,7 +256,7 @@ __global__ void __launch_bounds__(kElemBlock) k_element_affine(DevArrays d, KPar
 
   // ---- strain ----
   T vx[9], vy[9];
-  load_velocity<T>(D, d.v, ex, ey, vx, vy);
+  load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
   T E11[NS], E12[NS], E22[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -277,7 +282,6 @@ __global__ void __launch_bounds__(kElemBlock) k_element_affine(DevArrays d, KPar
   double Hc[NA], Ac[NA];
   load_ice<NA>(d, D, el, Hc, Ac);
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
-  T R11[NS], R12[NS], R22[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
@@ -305,10 +309,9 @@ __global__ void __launch_bounds__(kElemBlock) k_element_affine(DevArrays d, KPar
       }
     }
   }
-  relax_store<NS, T, TS>(d, D, el, p, R11, R12, R22);
+  relax<NS, T, TS>(S_in, (size_t)D.ne, el, p, R11, R12, R22);
 
   // ---- divergence, element part ----
-  T fx[9], fy[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     T bx11 = 0, be11 = 0, bx12 = 0, be12 = 0, bx22 = 0, be22 = 0;
@@ -330,32 +333,27 @@ __global__ void __launch_bounds__(kElemBlock) k_element_affine(DevArrays d, KPar
     fx[a] = -((J11 * bx11 - J01 * bx12) + (J00 * be12 - J10 * be11));
     fy[a] = -((J11 * bx12 - J01 * bx22) + (J00 * be22 - J10 * be12));
   }
-  store_forces<T, TS>(d, D, el, fx, fy);
 }
 
 // ---------------------------------------------------------------------------
-// Element phase, general bilinear cells: strain -> stress update -> forces.
-//   T   type of the contractions (double, or float in mixed precision)
-//   TS  storage type of S and of the nodal forces
+// Element update, general bilinear cells: Jacobian per Gauss point, local
+// mass matrix M_e = Psi W_e Psi^T factorised per element.
 // ---------------------------------------------------------------------------
 template <int NS, int NA, class T, class TS>
-__global__ void __launch_bounds__(kElemBlock) k_element_general(DevArrays d, KParams p,
-                                                                const Blk *blks) {
+__device__ __forceinline__ void element_general(const DevArrays &d, const DomDev &D,
+                                                const KParams &p, const double *v_in,
+                                                const TS *S_in, int el, int ex, int ey,
+                                                T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
+                                                T (&fx)[9], T (&fy)[9]) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
-  const Blk blk = blks[blockIdx.x];
-  const DomDev D = d.doms[blk.dom];
-  const int el = blk.first + (int)threadIdx.x;
-  if (el >= D.ne) return;
-  const int ex = el % D.nx, ey = el / D.nx;
-
   const Cell<T> cell = load_cell<T>(D, d.vert, ex, ey);
   Ldl<NS, T> mass;
   mass.template build<Q>(cell);
 
   // ---- strain ----
   T vx[9], vy[9];
-  load_velocity<T>(D, d.v, ex, ey, vx, vy);
+  load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
   T E11[NS], E12[NS], E22[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) E11[k] = E12[k] = E22[k] = T(0);
@@ -398,7 +396,6 @@ __global__ void __launch_bounds__(kElemBlock) k_element_general(DevArrays d, KPa
   double Hc[NA], Ac[NA];
   load_ice<NA>(d, D, el, Hc, Ac);
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
-  T R11[NS], R12[NS], R22[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
@@ -432,11 +429,10 @@ __global__ void __launch_bounds__(kElemBlock) k_element_general(DevArrays d, KPa
   mass.solve(R11);
   mass.solve(R12);
   mass.solve(R22);
-  relax_store<NS, T, TS>(d, D, el, p, R11, R12, R22);
+  relax<NS, T, TS>(S_in, (size_t)D.ne, el, p, R11, R12, R22);
 
   // ---- divergence, element part: f[a] = -sum_q w_q |J_q| sigma(q) grad phi_a(q)
   //      = -sum_q (dphi_a/dxi Gxi + dphi_a/deta Geta) with G = w_q sigma adj(J)^T ----
-  T fx[9], fy[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) fx[a] = fy[a] = T(0);
 #pragma unroll
@@ -470,28 +466,89 @@ __global__ void __launch_bounds__(kElemBlock) k_element_general(DevArrays d, KPa
       }
     }
   }
-  store_forces<T, TS>(d, D, el, fx, fy);
+}
+
+template <int NS, int NA, class T, class TS, bool AFF>
+__device__ __forceinline__ void element_update(const DevArrays &d, const DomDev &D,
+                                               const KParams &p, const double *v_in,
+                                               const TS *S_in, int el, int ex, int ey,
+                                               T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
+                                               T (&fx)[9], T (&fy)[9]) {
+  if constexpr (AFF)
+    element_affine<NS, NA, T, TS>(d, D, p, v_in, S_in, el, ex, ey, R11, R12, R22, fx, fy);
+  else
+    element_general<NS, NA, T, TS>(d, D, p, v_in, S_in, el, ex, ey, R11, R12, R22, fx, fy);
+}
+
+// Velocity update of one interior node:
+//   (c (1+beta) + d) v + b k x v = c beta v^{p-1} + g + d v_o + F
+// with c = M^H/dt, b = f M^H, d = m^A rho_o C_o |v_o - v^{p-1}| and
+// g = c v^n + m^A tau_a (node constants nc[6][nn] of the step), closed form.
+__device__ __forceinline__ void velocity_update(const KParams &p, const double *nc, size_t nn,
+                                                int j, double ux, double uy, double Fx,
+                                                double Fy, double &vx, double &vy) {
+  const double c = nc[j], ko = nc[nn + j], gx = nc[2 * nn + j], gy = nc[3 * nn + j];
+  const double ox = nc[4 * nn + j], oy = nc[5 * nn + j];
+  const double dox = ox - ux, doy = oy - uy;
+  const double dd = ko * sqrt(dox * dox + doy * doy);
+  const double bb = c * p.f_dt;
+  const double cb = c * p.beta;
+  const double rx = cb * ux + gx + dd * ox + Fx;
+  const double ry = cb * uy + gy + dd * oy + Fy;
+  const double aa = c * (1.0 + p.beta) + dd;
+  const double den = aa * aa + bb * bb;
+  if (den == 0.0) {
+    vx = 0.0;
+    vy = 0.0;
+  } else {
+    const double inv = 1.0 / den;
+    vx = (aa * rx + bb * ry) * inv;
+    vy = (aa * ry - bb * rx) * inv;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Node phase: deterministic gather of the element forces + velocity update
-//   (c (1+beta) + d) v + b k x v = c beta v^{p-1} + g + d v_o + F
-// with c = M^H/dt, b = f M^H, d = m^A rho_o C_o |v_o - v^{p-1}| and
-// g = c v^n + m^A tau_a, solved in closed form; v = 0 on the boundary.
+// Two-phase subcycle, element kernel: element update, S written in place
+// (each lane reads and writes only its own element), forces to scratch.
+// ---------------------------------------------------------------------------
+template <int NS, int NA, class T, class TS, bool AFF>
+__global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p, const Blk *blks,
+                                                        Bufs b) {
+  const Blk blk = blks[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int el = blk.first + (int)threadIdx.x;
+  if (el >= D.ne) return;
+  const int ex = el % D.nx, ey = el / D.nx;
+  const DomBufs<TS> B(b, D, NS);
+  T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
+  element_update<NS, NA, T, TS, AFF>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx, fy);
+  store_stress<NS, T, TS>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
+  const size_t ne = (size_t)D.ne;
+  TS *fe = static_cast<TS *>(d.fe) + (size_t)18 * D.elem_off;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    fe[a * ne + el] = TS(fx[a]);
+    fe[(9 + a) * ne + el] = TS(fy[a]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-phase subcycle, node kernel: deterministic gather of the element forces
+// (ascending element order, no atomics) + velocity update, v in place.
 // ---------------------------------------------------------------------------
 template <class TF>
-__global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p) {
+__global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p, Bufs b) {
   const Blk blk = d.nblk[blockIdx.x];
   const DomDev D = d.doms[blk.dom];
   const int j = blk.first + (int)threadIdx.x;
   if (j >= D.nn) return;
   const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
   const int ix = j % NX, iy = j / NX;
-  double *vx = d.v + 2 * (size_t)D.node_off;
-  double *vy = vx + D.nn;
+  const double *vin = b.v_in + 2 * (size_t)D.node_off;
+  double *vout = b.v_out + 2 * (size_t)D.node_off;
   if (ix == 0 || iy == 0 || ix == NX - 1 || iy == NY - 1) {
-    vx[j] = 0.0;
-    vy[j] = 0.0;
+    vout[j] = 0.0;
+    vout[D.nn + j] = 0.0;
     return;
   }
   // elements around node (ix, iy): for an odd index the one element whose
@@ -504,35 +561,91 @@ __global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p) {
   const size_t ne = (size_t)D.ne;
   double Fx = 0.0, Fy = 0.0;
   for (int t = 0; t < ney; ++t) {
-    const int ey = ey0 + t, b = b0 - 2 * t;
+    const int ey = ey0 + t, bb = b0 - 2 * t;
     for (int s = 0; s < nex; ++s) {
       const int ex = ex0 + s, c = c0 - 2 * s;
       const size_t e = (size_t)ey * D.nx + ex;
-      const int a = 3 * b + c;
+      const int a = 3 * bb + c;
       Fx += (double)fe[a * ne + e];
       Fy += (double)fe[(9 + a) * ne + e];
     }
   }
+  double vx, vy;
+  velocity_update(p, d.nc + (size_t)6 * D.node_off, (size_t)D.nn, j, vin[j], vin[D.nn + j], Fx,
+                  Fy, vx, vy);
+  vout[j] = vx;
+  vout[D.nn + j] = vy;
+}
+
+// ---------------------------------------------------------------------------
+// Fused subcycle: one workgroup per tile of kTileEX x kTileEY elements. The
+// tile's first column and row are a halo (the elements left of and below the
+// owned (kTileEX-1) x (kTileEY-1) block): their forces are recomputed here
+// (their stress is not stored; its owner stores it), so every node the tile
+// owns -- CG2 columns [2 x0, 2 x0 + 2 (kTileEX-1)) and rows likewise, plus the
+// last column / row of the domain for the last tile -- finds the forces of
+// all its elements in LDS. The forces never leave the chip. v and S are read
+// from the *_in buffers and written to the *_out buffers (double buffering:
+// neighbouring tiles read the old values while this one writes the new).
+// ---------------------------------------------------------------------------
+template <int NS, int NA, class T, class TS, bool AFF>
+__global__ void __launch_bounds__(kTileThreads) k_subcycle(DevArrays d, KParams p,
+                                                           const Tile *tiles, Bufs b) {
+  constexpr int EX = kTileEX, EY = kTileEY, TX = EX - 1, TY = EY - 1;
+  __shared__ T fl[18][EX * EY];
+  const Tile t = tiles[blockIdx.x];
+  const DomDev D = d.doms[t.dom];
+  const DomBufs<TS> B(b, D, NS);
+  const int tid = (int)threadIdx.x;
+  {
+    const int lx = tid % EX, ly = tid / EX;
+    const int ex = t.x0 - 1 + lx, ey = t.y0 - 1 + ly;
+    if (ex >= 0 && ey >= 0 && ex < D.nx && ey < D.ny) {
+      const int el = ey * D.nx + ex;
+      T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
+      element_update<NS, NA, T, TS, AFF>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx,
+                                         fy);
+      if (lx > 0 && ly > 0) store_stress<NS, T, TS>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        fl[a][tid] = fx[a];
+        fl[9 + a][tid] = fy[a];
+      }
+    }
+  }
+  __syncthreads();
+  const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
+  const int ix0 = 2 * t.x0, iy0 = 2 * t.y0;
+  const int ix1 = (t.x0 + TX >= D.nx) ? NX : ix0 + 2 * TX;
+  const int iy1 = (t.y0 + TY >= D.ny) ? NY : iy0 + 2 * TY;
+  const int w = ix1 - ix0, n = w * (iy1 - iy0);
   const double *nc = d.nc + (size_t)6 * D.node_off;
-  const size_t nn = (size_t)D.nn;
-  const double c = nc[j], ko = nc[nn + j], gx = nc[2 * nn + j], gy = nc[3 * nn + j];
-  const double ox = nc[4 * nn + j], oy = nc[5 * nn + j];
-  const double ux = vx[j], uy = vy[j];
-  const double dox = ox - ux, doy = oy - uy;
-  const double dd = ko * sqrt(dox * dox + doy * doy);
-  const double bb = c * p.f_dt;
-  const double cb = c * p.beta;
-  const double rx = cb * ux + gx + dd * ox + Fx;
-  const double ry = cb * uy + gy + dd * oy + Fy;
-  const double aa = c * (1.0 + p.beta) + dd;
-  const double den = aa * aa + bb * bb;
-  if (den == 0.0) {
-    vx[j] = 0.0;
-    vy[j] = 0.0;
-  } else {
-    const double inv = 1.0 / den;
-    vx[j] = (aa * rx + bb * ry) * inv;
-    vy[j] = (aa * ry - bb * rx) * inv;
+  for (int k = tid; k < n; k += kTileThreads) {
+    const int ix = ix0 + k % w, iy = iy0 + k / w;
+    const int j = iy * NX + ix;
+    if (ix == 0 || iy == 0 || ix == NX - 1 || iy == NY - 1) {
+      B.v_out[j] = 0.0;
+      B.v_out[D.nn + j] = 0.0;
+      continue;
+    }
+    const int ney = (iy & 1) ? 1 : 2, nex = (ix & 1) ? 1 : 2;
+    const int ey0 = (iy & 1) ? (iy - 1) / 2 : iy / 2 - 1;
+    const int ex0 = (ix & 1) ? (ix - 1) / 2 : ix / 2 - 1;
+    const int b0 = (iy & 1) ? 1 : 2, c0 = (ix & 1) ? 1 : 2;
+    double Fx = 0.0, Fy = 0.0;
+    for (int tt = 0; tt < ney; ++tt) {
+      const int ly = ey0 + tt - t.y0 + 1, bb = b0 - 2 * tt;
+      for (int ss = 0; ss < nex; ++ss) {
+        const int lx = ex0 + ss - t.x0 + 1, c = c0 - 2 * ss;
+        const int a = 3 * bb + c, le = ly * EX + lx;
+        Fx += (double)fl[a][le];
+        Fy += (double)fl[9 + a][le];
+      }
+    }
+    double vx, vy;
+    velocity_update(p, nc, (size_t)D.nn, j, B.v_in[j], B.v_in[D.nn + j], Fx, Fy, vx, vy);
+    B.v_out[j] = vx;
+    B.v_out[D.nn + j] = vy;
   }
 }
 
@@ -543,7 +656,8 @@ __global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p) {
 // g = c v^n + m^A tau_a (2), ocean velocity (2).
 // ---------------------------------------------------------------------------
 template <int NS, int NA>
-__global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams p) {
+__global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams p,
+                                                           const double *v) {
   using Q = Quad<Ngp<NS>::value>;
   const Blk blk = d.nblk[blockIdx.x];
   const DomDev D = d.doms[blk.dom];
@@ -609,8 +723,8 @@ __global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams 
   const size_t nn = (size_t)D.nn;
   nc[j] = c;
   nc[nn + j] = mA * p.rhoCo;
-  nc[2 * nn + j] = c * d.v[o + j] + mA * (p.rhoCa * sp * wx);
-  nc[3 * nn + j] = c * d.v[o + D.nn + j] + mA * (p.rhoCa * sp * wy);
+  nc[2 * nn + j] = c * v[o + j] + mA * (p.rhoCa * sp * wx);
+  nc[3 * nn + j] = c * v[o + D.nn + j] + mA * (p.rhoCa * sp * wy);
   nc[4 * nn + j] = d.ocean[o + j];
   nc[5 * nn + j] = d.ocean[o + D.nn + j];
 }
@@ -690,15 +804,16 @@ inline unsigned grid_for(size_t n, unsigned block) {
 // Launchers
 // ---------------------------------------------------------------------------
 template <int NS, int NA>
-static hipError_t begin_step_t(const DevArrays &d, const KParams &p, int n_nblk, hipStream_t s) {
-  hipLaunchKernelGGL((k_begin_step<NS, NA>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p);
+static hipError_t begin_step_t(const DevArrays &d, const KParams &p, const double *v, int n_nblk,
+                               hipStream_t s) {
+  hipLaunchKernelGGL((k_begin_step<NS, NA>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p, v);
   return hipGetLastError();
 }
 
-hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int n_s, int n_nblk,
-                             hipStream_t s) {
+hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int n_s,
+                             const double *v, int n_nblk, hipStream_t s) {
 #define MEVP_BS(NS_, NA_) \
-  if (n_s == NS_ && n_a == NA_) return begin_step_t<NS_, NA_>(d, p, n_nblk, s);
+  if (n_s == NS_ && n_a == NA_) return begin_step_t<NS_, NA_>(d, p, v, n_nblk, s);
   MEVP_BS(3, 1) MEVP_BS(3, 3) MEVP_BS(3, 6)
   MEVP_BS(6, 1) MEVP_BS(6, 3) MEVP_BS(6, 6)
   MEVP_BS(8, 1) MEVP_BS(8, 3) MEVP_BS(8, 6)
@@ -706,28 +821,38 @@ hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int 
   return hipErrorInvalidValue;
 }
 
-template <int NS, int NA>
-static hipError_t element_t(const DevArrays &d, const KParams &p, bool mixed, const Blk *blks,
-                            int n_aff, int n_gen, hipStream_t s) {
-  if (n_aff > 0) {
-    if (mixed)
-      hipLaunchKernelGGL((k_element_affine<NS, NA, float, float>), dim3(n_aff), dim3(kElemBlock), 0, s, d, p, blks);
-    else
-      hipLaunchKernelGGL((k_element_affine<NS, NA, double, double>), dim3(n_aff), dim3(kElemBlock), 0, s, d, p, blks);
-  }
-  if (n_gen > 0) {
-    if (mixed)
-      hipLaunchKernelGGL((k_element_general<NS, NA, float, float>), dim3(n_gen), dim3(kElemBlock), 0, s, d, p, blks + n_aff);
-    else
-      hipLaunchKernelGGL((k_element_general<NS, NA, double, double>), dim3(n_gen), dim3(kElemBlock), 0, s, d, p, blks + n_aff);
-  }
+// Two-phase subcycle: element kernel(s) (parallelogram blocks, general
+// blocks), then the node kernel.
+template <int NS, int NA, class T>
+static hipError_t two_phase_t(const DevArrays &d, const KParams &p, const Launch &L, Bufs b,
+                              hipStream_t s) {
+  if (L.n_aff > 0)
+    hipLaunchKernelGGL((k_element<NS, NA, T, T, true>), dim3(L.n_aff), dim3(kElemBlock), 0, s, d, p,
+                       d.eblk, b);
+  if (L.n_gen > 0)
+    hipLaunchKernelGGL((k_element<NS, NA, T, T, false>), dim3(L.n_gen), dim3(kElemBlock), 0, s, d, p,
+                       d.eblk + L.n_aff, b);
+  return hipGetLastError();
+}
+
+// Fused subcycle: tile kernel(s), parallelogram tiles first.
+template <int NS, int NA, class T>
+static hipError_t fused_t(const DevArrays &d, const KParams &p, const Launch &L, Bufs b,
+                          hipStream_t s) {
+  if (L.n_aff > 0)
+    hipLaunchKernelGGL((k_subcycle<NS, NA, T, T, true>), dim3(L.n_aff), dim3(kTileThreads), 0, s, d,
+                       p, d.tiles, b);
+  if (L.n_gen > 0)
+    hipLaunchKernelGGL((k_subcycle<NS, NA, T, T, false>), dim3(L.n_gen), dim3(kTileThreads), 0, s, d,
+                       p, d.tiles + L.n_aff, b);
   return hipGetLastError();
 }
 
 hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, int n_a, bool mixed,
-                                int n_aff, int n_gen, hipStream_t s) {
-#define MEVP_EL(NS_, NA_) \
-  if (n_s == NS_ && n_a == NA_) return element_t<NS_, NA_>(d, p, mixed, d.eblk, n_aff, n_gen, s);
+                                const Launch &L, Bufs b, hipStream_t s) {
+#define MEVP_EL(NS_, NA_)                                                                   \
+  if (n_s == NS_ && n_a == NA_)                                                             \
+    return mixed ? two_phase_t<NS_, NA_, float>(d, p, L, b, s) : two_phase_t<NS_, NA_, double>(d, p, L, b, s);
   MEVP_EL(3, 1) MEVP_EL(3, 3) MEVP_EL(3, 6)
   MEVP_EL(6, 1) MEVP_EL(6, 3) MEVP_EL(6, 6)
   MEVP_EL(8, 1) MEVP_EL(8, 3) MEVP_EL(8, 6)
@@ -735,18 +860,30 @@ hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, i
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_cell_shape, dim3(grid_for((size_t)ne, kElemBlock)), dim3(kElemBlock), 0, s, d,
-                     dom, flag);
+hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, int n_nblk, Bufs b,
+                             hipStream_t s) {
+  if (mixed)
+    hipLaunchKernelGGL((k_node<float>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p, b);
+  else
+    hipLaunchKernelGGL((k_node<double>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p, b);
   return hipGetLastError();
 }
 
-hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, int n_nblk,
-                             hipStream_t s) {
-  if (mixed)
-    hipLaunchKernelGGL((k_node<float>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p);
-  else
-    hipLaunchKernelGGL((k_node<double>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p);
+hipError_t launch_fused_subcycle(const DevArrays &d, const KParams &p, int n_s, int n_a, bool mixed,
+                                 const Launch &L, Bufs b, hipStream_t s) {
+#define MEVP_FU(NS_, NA_)                                                                   \
+  if (n_s == NS_ && n_a == NA_)                                                             \
+    return mixed ? fused_t<NS_, NA_, float>(d, p, L, b, s) : fused_t<NS_, NA_, double>(d, p, L, b, s);
+  MEVP_FU(3, 1) MEVP_FU(3, 3) MEVP_FU(3, 6)
+  MEVP_FU(6, 1) MEVP_FU(6, 3) MEVP_FU(6, 6)
+  MEVP_FU(8, 1) MEVP_FU(8, 3) MEVP_FU(8, 6)
+#undef MEVP_FU
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_shape, dim3(grid_for((size_t)ne, kElemBlock)), dim3(kElemBlock), 0, s, d,
+                     dom, flag);
   return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ from . import build as _build
 
 FP64 = 0
 MIXED = 1
+STRATEGIES = {"fused": 0, "two_phase": 1}
 _PREC = {"fp64": FP64, "f64": FP64, "mixed": MIXED}
 
 STATUS = {0: "MEVP_OK", -1: "MEVP_EINVAL", -2: "MEVP_ENOMEM", -3: "MEVP_EDEVICE",
@@ -43,7 +44,8 @@ class CDomain(C.Structure):
 
 _lib = None
 
-EXPORTS = ["mevp_default_params", "mevp_workspace_size", "mevp_create", "mevp_set_params",
+EXPORTS = ["mevp_default_params", "mevp_workspace_size", "mevp_create", "mevp_set_strategy",
+           "mevp_set_params",
            "mevp_set_geometry", "mevp_set_fields", "mevp_set_forcing", "mevp_set_state",
            "mevp_step", "mevp_begin_step", "mevp_subcycles", "mevp_get_state", "mevp_sync",
            "mevp_check_inputs", "mevp_check_state", "mevp_timing_enable", "mevp_timing_read",
@@ -70,6 +72,7 @@ def lib():
     L.mevp_create.argtypes = [C.POINTER(CParams), i, C.POINTER(CDomain), i, vp, C.c_size_t, vp,
                               C.POINTER(vp)]
     L.mevp_set_params.argtypes = [vp, C.POINTER(CParams)]
+    L.mevp_set_strategy.argtypes = [vp, i]
     L.mevp_set_geometry.argtypes = [vp, i, dp]
     L.mevp_set_fields.argtypes = [vp, i, dp, dp]
     L.mevp_set_forcing.argtypes = [vp, i, dp, dp]
@@ -176,7 +179,7 @@ class Context:
     device, its stream the current torch stream at creation."""
 
     def __init__(self, domains, params: Params | None = None, precision: str = "fp64",
-                 stream=None):
+                 stream=None, strategy: str = "fused"):
         import torch
         self._torch = torch
         self.domains = [d if isinstance(d, Domain) else Domain(*d) for d in domains]
@@ -195,6 +198,7 @@ class Context:
             len(self.domains), C.c_void_p(self.workspace.data_ptr()), C.c_size_t(size),
             C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
+        self.set_strategy(strategy)
 
     # -- helpers --------------------------------------------------------
     def _arg(self, t, shape, name):
@@ -214,6 +218,10 @@ class Context:
         return self.domains[dom]
 
     # -- copy-in --------------------------------------------------------
+    def set_strategy(self, strategy: str):
+        _check("mevp_set_strategy", lib().mevp_set_strategy(self._h, STRATEGIES[strategy]))
+        self.strategy = strategy
+
     def set_params(self, params: Params):
         _check("mevp_set_params", lib().mevp_set_params(self._h, C.byref(params.to_c())))
         self.params = params

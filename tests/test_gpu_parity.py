@@ -55,18 +55,19 @@ WHOLE_RUNS = [
 ]
 
 
+@pytest.mark.parametrize("strategy", ["fused", "two_phase"])
 @pytest.mark.parametrize("case", WHOLE_RUNS, ids=lambda c: "x".join(map(str, c[:4])))
-def test_whole_run_fp64(case):
+def test_whole_run_fp64(case, strategy):
     nx, ny, ns, na, h, pert, ho, steps, nsub = case
     d = make_domain(nx, ny, ns, na, seed=nx * 100 + ny, h=h, perturb=pert, ho_amp=ho)
     if nx == 1 and ny == 1:
         # the gyre and the current vanish at the single interior node: drive it with a
         # uniform wind so that v and S12 are not pure rounding noise
         d.wind[0], d.wind[1] = 4.0, -3.0
-    log(f"case {case}")
-    (v, S), = gpu_run([d], steps, nsub)
+    log(f"case {case} {strategy}")
+    (v, S), = gpu_run([d], steps, nsub, strategy=strategy)
     vr, Sr = oracle_run(d, steps, nsub)
-    _assert_close(field_errors(v, S, vr, Sr), TOL64, f"fp64 {nx}x{ny} ns={ns} na={na}")
+    _assert_close(field_errors(v, S, vr, Sr), TOL64, f"fp64 {nx}x{ny} ns={ns} na={na} {strategy}")
 
 
 def test_whole_run_32x32_dg1_workload():
@@ -185,3 +186,17 @@ def test_equation_relaxation_form():
     _assert_close(field_errors(v, S, vr, Sr), TOL64, "relax_form=1")
     v0, S0 = oracle_run(d, 1, 40)
     assert max(field_errors(v0, S0, vr, Sr).values()) > 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("perturb", [0.0, 0.1])
+def test_fused_equals_two_phase(precision, perturb):
+    """Both launch strategies sum the nodal forces in the same order from the same
+    element computation: the results agree bitwise, over tile boundaries and
+    ragged tiles, for parallelogram and general cells, over several steps."""
+    d = make_domain(173, 61, 6, 1, seed=61, h=2e3, perturb=perturb)
+    state = random_state(d.nx, d.ny, d.n_s, seed=5)
+    a = gpu_run([d], 2, 25, precision=precision, states=[state], strategy="fused")[0]
+    b = gpu_run([d], 2, 25, precision=precision, states=[state], strategy="two_phase")[0]
+    log(f"fused vs two-phase {precision} perturb={perturb}: max |dv| {np.abs(a[0] - b[0]).max():.3e}")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
