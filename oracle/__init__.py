@@ -46,6 +46,8 @@ def lib():
         L.or_stress_gauss.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp, dp, dp, dp]
         L.or_project.argtypes = [C.c_void_p, dp, C.c_int, dp]
         L.or_num_threads.restype = C.c_int
+        L.or_advect.argtypes = [C.c_void_p, C.c_double, dp, dp, dp]
+        L.or_advect_rate.argtypes = [C.c_void_p, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -189,7 +191,21 @@ class Mesh:
             v, S = self.step(p, H, A, wind, ocean, v, S, n_sub)
         return v, S
 
+    def advect(self, dt, v, H, A):
+        """One advection step of H and A (returns new arrays)."""
+        v = _f64(v)
+        H = _f64(H).copy()
+        A = _f64(A).copy()
+        lib().or_advect(self._h, float(dt), _p(v), _p(H), _p(A))
+        return H, A
+
     # --- test hooks ----------------------------------------------------
+    def advect_rate(self, v, U):
+        v, U = _f64(v), _f64(U)
+        L = np.zeros((self.na, self.ne))
+        lib().or_advect_rate(self._h, _p(v), _p(U), _p(L))
+        return L
+
     def element_geometry(self, e):
         wd = np.zeros(self.ng)
         gx = np.zeros((9, self.ng))

@@ -38,6 +38,17 @@
  *     Coriolis term implicit (a closed-form 2x2 solve).
  *  R12 boundary: v = 0 on all CG2 nodes of the outer boundary.
  *  R13 state: S persists between time steps, v^n is v at the start of a step.
+ *  R14 advection (Sec. 2 and Eq. (si:ad): DG in space with the standard upwind
+ *     flux, explicit Runge-Kutta in time; sources S_H = S_A = 0): for each DG
+ *     test function psi_k of the n_a-dof space,
+ *       M_e dU/dt = int_K U v.grad psi_k - sum over the 4 edges of
+ *                   int_edge (v.n) U_up psi_k,
+ *     with U_up the trace of K where v.n >= 0 and of the neighbour otherwise
+ *     (the trace of K on the domain boundary, where v = 0 anyway), v the
+ *     CG2 velocity at the start of the step, held fixed, 3x3 Gauss points in
+ *     the cell and 3 per edge, and the three-stage SSP Runge-Kutta scheme
+ *     U1 = U + dt L(U), U2 = 3/4 U + 1/4 (U1 + dt L(U1)),
+ *     U^{n+1} = 1/3 U + 2/3 (U2 + dt L(U2)).
  */
 #include "mevp_oracle.h"
 
@@ -63,6 +74,7 @@ struct or_mesh {
   double *dphix; /* [ne][9][ng] */
   double *dphiy; /* [ne][9][ng] */
   double *chol;  /* [ne][ns][ns], lower triangle */
+  double *vx, *vy; /* copy of the vertices [(nx+1)(ny+1)] */
 };
 
 int or_num_threads(void) {
@@ -231,11 +243,16 @@ or_mesh *or_mesh_create(int nx, int ny, int ns, int na, const double *vertices) 
   m->dphix = (double *)malloc(sizeof(double) * ne * 9 * ng);
   m->dphiy = (double *)malloc(sizeof(double) * ne * 9 * ng);
   m->chol = (double *)malloc(sizeof(double) * ne * ns * ns);
-  if (!m->wdet || !m->dphix || !m->dphiy || !m->chol) {
+  size_t nv = (size_t)(nx + 1) * (ny + 1);
+  m->vx = (double *)malloc(sizeof(double) * nv);
+  m->vy = (double *)malloc(sizeof(double) * nv);
+  if (!m->wdet || !m->dphix || !m->dphiy || !m->chol || !m->vx || !m->vy) {
     or_mesh_destroy(m);
     return NULL;
   }
   const double *VX = vertices, *VY = vertices + (size_t)(nx + 1) * (ny + 1);
+  memcpy(m->vx, VX, sizeof(double) * nv);
+  memcpy(m->vy, VY, sizeof(double) * nv);
   int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
   for (long e = 0; e < (long)ne; ++e) {
@@ -291,6 +308,8 @@ void or_mesh_destroy(or_mesh *m) {
   free(m->dphix);
   free(m->dphiy);
   free(m->chol);
+  free(m->vx);
+  free(m->vy);
   free(m);
 }
 
@@ -575,6 +594,166 @@ void or_velocity(const or_mesh *m, const or_params *p, const double *F, const do
       v[nn + j] = (a * ry - b * rx) / den;
     }
   }
+}
+
+/* ---------------------------------------------------------------------------
+ * Advection of H and A (R14)
+ * ------------------------------------------------------------------------- */
+
+/* d psi_k / d xi and d psi_k / d eta (R6). */
+static void dg_basis_grad(int k, double xi, double eta, double *dxi, double *deta) {
+  double s = xi - 0.5, t = eta - 0.5;
+  switch (k) {
+    case 0: *dxi = 0.0; *deta = 0.0; return;
+    case 1: *dxi = 1.0; *deta = 0.0; return;
+    case 2: *dxi = 0.0; *deta = 1.0; return;
+    case 3: *dxi = 2.0 * s; *deta = 0.0; return;
+    case 4: *dxi = t; *deta = s; return;
+    case 5: *dxi = 0.0; *deta = 2.0 * t; return;
+  }
+  *dxi = 0.0;
+  *deta = 0.0;
+}
+
+/* reference point of parameter u in [0,1] on edge ed of the reference square,
+ * traversed counter-clockwise: 0 bottom, 1 right, 2 top, 3 left */
+static void edge_point(int ed, double u, double *xi, double *eta) {
+  switch (ed) {
+    case 0: *xi = u; *eta = 0.0; return;
+    case 1: *xi = 1.0; *eta = u; return;
+    case 2: *xi = 1.0 - u; *eta = 1.0; return;
+    default: *xi = 0.0; *eta = 1.0 - u; return;
+  }
+}
+
+/* the same physical point seen from the neighbour across edge ed */
+static void edge_point_nb(int ed, double u, double *xi, double *eta) {
+  switch (ed) {
+    case 0: *xi = u; *eta = 1.0; return;
+    case 1: *xi = 0.0; *eta = u; return;
+    case 2: *xi = 1.0 - u; *eta = 0.0; return;
+    default: *xi = 1.0; *eta = 1.0 - u; return;
+  }
+}
+
+static double dg_value(int na, const double *U, size_t ne, size_t e, double xi, double eta) {
+  double s = 0.0;
+  for (int k = 0; k < na; ++k) s += U[k * ne + e] * dg_basis(k, xi, eta);
+  return s;
+}
+
+/* L(U) = M_e^-1 R_e(U) for one field, all elements. */
+static void advect_rate(const or_mesh *m, const double *v, const double *U, double *L) {
+  size_t ne = (size_t)m->nx * m->ny, nn = (size_t)(2 * m->nx + 1) * (2 * m->ny + 1);
+  int na = m->na;
+  double gp[3], gw[3];
+  gauss_rule(3, gp, gw);
+  const double *VX = m->vx, *VY = m->vy;
+#pragma omp parallel for schedule(static)
+  for (long e = 0; e < (long)ne; ++e) {
+    int ex = (int)(e % m->nx), ey = (int)(e / m->nx);
+    int vi[4] = {vert_index(m, ex, ey), vert_index(m, ex + 1, ey), vert_index(m, ex, ey + 1),
+                 vert_index(m, ex + 1, ey + 1)};
+    double X[4], Y[4], vxe[9], vye[9];
+    for (int i = 0; i < 4; ++i) {
+      X[i] = VX[vi[i]];
+      Y[i] = VY[vi[i]];
+    }
+    for (int a = 0; a < 9; ++a) {
+      int j = local_to_global(m, (int)e, a);
+      vxe[a] = v[j];
+      vye[a] = v[nn + j];
+    }
+    double R[6] = {0, 0, 0, 0, 0, 0}, M[36];
+    memset(M, 0, sizeof M);
+    /* cell integral and mass matrix */
+    for (int qy = 0; qy < 3; ++qy)
+      for (int qx = 0; qx < 3; ++qx) {
+        double xi = gp[qx], eta = gp[qy], w = gw[qx] * gw[qy];
+        double J00 = (1.0 - eta) * (X[1] - X[0]) + eta * (X[3] - X[2]);
+        double J01 = (1.0 - xi) * (X[2] - X[0]) + xi * (X[3] - X[1]);
+        double J10 = (1.0 - eta) * (Y[1] - Y[0]) + eta * (Y[3] - Y[2]);
+        double J11 = (1.0 - xi) * (Y[2] - Y[0]) + xi * (Y[3] - Y[1]);
+        double det = J00 * J11 - J01 * J10;
+        double ux = 0.0, uy = 0.0;
+        for (int a = 0; a < 9; ++a) {
+          double ph = lag2(a % 3, xi) * lag2(a / 3, eta);
+          ux += vxe[a] * ph;
+          uy += vye[a] * ph;
+        }
+        double Uq = dg_value(na, U, ne, (size_t)e, xi, eta);
+        for (int k = 0; k < na; ++k) {
+          double dxi, deta;
+          dg_basis_grad(k, xi, eta, &dxi, &deta);
+          double gx = (J11 * dxi - J10 * deta) / det; /* grad psi = J^-T (d/dxi, d/deta) */
+          double gy = (-J01 * dxi + J00 * deta) / det;
+          R[k] += w * det * Uq * (ux * gx + uy * gy);
+          for (int l = 0; l < na; ++l)
+            M[k * na + l] += w * det * dg_basis(k, xi, eta) * dg_basis(l, xi, eta);
+        }
+      }
+    /* edge fluxes; scaled outward normal n L = (t_y, -t_x) of the edge vector t */
+    const int from[4] = {0, 1, 3, 2}, to[4] = {1, 3, 2, 0};
+    const int nbx[4] = {0, 1, 0, -1}, nby[4] = {-1, 0, 1, 0};
+    for (int ed = 0; ed < 4; ++ed) {
+      double tx = X[to[ed]] - X[from[ed]], ty = Y[to[ed]] - Y[from[ed]];
+      double nlx = ty, nly = -tx;
+      int fx = ex + nbx[ed], fy = ey + nby[ed];
+      int has_nb = fx >= 0 && fy >= 0 && fx < m->nx && fy < m->ny;
+      size_t f = has_nb ? (size_t)fy * m->nx + fx : 0;
+      for (int g = 0; g < 3; ++g) {
+        double xi, eta;
+        edge_point(ed, gp[g], &xi, &eta);
+        double ux = 0.0, uy = 0.0;
+        for (int a = 0; a < 9; ++a) {
+          double ph = lag2(a % 3, xi) * lag2(a / 3, eta);
+          ux += vxe[a] * ph;
+          uy += vye[a] * ph;
+        }
+        double vn = ux * nlx + uy * nly;
+        double Uup;
+        if (vn >= 0.0 || !has_nb) {
+          Uup = dg_value(na, U, ne, (size_t)e, xi, eta);
+        } else {
+          double xn, en;
+          edge_point_nb(ed, gp[g], &xn, &en);
+          Uup = dg_value(na, U, ne, f, xn, en);
+        }
+        for (int k = 0; k < na; ++k) R[k] -= gw[g] * vn * Uup * dg_basis(k, xi, eta);
+      }
+    }
+    double Lc[36];
+    if (cholesky(na, M, Lc) != 0) { /* cells were validated at mesh creation */
+      for (int k = 0; k < na; ++k) L[k * ne + e] = 0.0;
+      continue;
+    }
+    chol_solve(na, Lc, R);
+    for (int k = 0; k < na; ++k) L[k * ne + e] = R[k];
+  }
+}
+
+/* One advection step of one field with the three-stage SSP Runge-Kutta scheme. */
+static void advect_field(const or_mesh *m, double dt, const double *v, double *U) {
+  size_t n = (size_t)m->na * m->nx * m->ny;
+  double *L = (double *)malloc(sizeof(double) * n);
+  double *U1 = (double *)malloc(sizeof(double) * n);
+  double *U2 = (double *)malloc(sizeof(double) * n);
+  advect_rate(m, v, U, L);
+  for (size_t i = 0; i < n; ++i) U1[i] = U[i] + dt * L[i];
+  advect_rate(m, v, U1, L);
+  for (size_t i = 0; i < n; ++i) U2[i] = 0.75 * U[i] + 0.25 * (U1[i] + dt * L[i]);
+  advect_rate(m, v, U2, L);
+  for (size_t i = 0; i < n; ++i) U[i] = U[i] / 3.0 + 2.0 / 3.0 * (U2[i] + dt * L[i]);
+  free(L), free(U1), free(U2);
+}
+
+void or_advect_rate(const or_mesh *m, const double *v, const double *U, double *L) {
+  advect_rate(m, v, U, L);
+}
+
+void or_advect(const or_mesh *m, double dt, const double *v, double *H, double *A) {
+  advect_field(m, dt, v, H);
+  advect_field(m, dt, v, A);
 }
 
 /* ---------------------------------------------------------------------------

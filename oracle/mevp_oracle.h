@@ -81,6 +81,12 @@ void or_velocity(const or_mesh *m, const or_params *p, const double *F, const do
                  const double *mA, const double *tau, const double *ocean, const double *vn,
                  double *v);
 
+/* Advection of H and A over dt with the CG2 velocity v held fixed
+ * (Sec. 2, Eq. (si:ad); reading R14 in mevp_oracle.c). H, A in/out. */
+void or_advect(const or_mesh *m, double dt, const double *v, double *H, double *A);
+/* Test hook: the advection rate L(U) = M^-1 R(U) of one field [na][ne]. */
+void or_advect_rate(const or_mesh *m, const double *v, const double *U, double *L);
+
 /* One time step = snapshot v^n, masses, air stress, then n_sub subcycles. */
 int or_step(const or_mesh *m, const or_params *p, const double *H, const double *A,
             const double *wind, const double *ocean, double *v, double *S, int n_sub);

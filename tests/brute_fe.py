@@ -155,3 +155,110 @@ class AffineMesh:
                 xs.append(ix * self.hx + iy * self.sh)
                 ys.append(iy * self.hy)
         return xs, ys
+
+
+# ---------------------------------------------------------------------------
+# DG upwind advection rate, exact (edges by exact 1D polynomial integrals)
+# ---------------------------------------------------------------------------
+def _pow_poly(base, n):
+    """(base)^n for base a dict {power: coef} in one variable u."""
+    out = {0: Fr(1)}
+    for _ in range(n):
+        nxt = {}
+        for i, a in out.items():
+            for j, b in base.items():
+                nxt[i + j] = nxt.get(i + j, Fr(0)) + a * b
+        out = nxt
+    return out
+
+
+def restrict(p, xi_of_u, eta_of_u):
+    """p(xi(u), eta(u)) as {power: coef}; xi_of_u, eta_of_u are {power: coef}."""
+    out = {}
+    for (i, j), c in p.t.items():
+        xi_p = _pow_poly(xi_of_u, i)
+        eta_p = _pow_poly(eta_of_u, j)
+        for a, ca in xi_p.items():
+            for b, cb in eta_p.items():
+                out[a + b] = out.get(a + b, Fr(0)) + c * ca * cb
+    return out
+
+
+def upoly_mul(*ps):
+    out = {0: Fr(1)}
+    for p in ps:
+        nxt = {}
+        for i, a in out.items():
+            for j, b in p.items():
+                nxt[i + j] = nxt.get(i + j, Fr(0)) + a * b
+        out = nxt
+    return out
+
+
+def upoly_int(p):
+    return sum((c / (i + 1) for i, c in p.items()), Fr(0))
+
+
+def upoly_at(p, u):
+    return sum((c * Fr(u) ** i for i, c in p.items()), Fr(0))
+
+
+U_ = {1: Fr(1)}
+ONE_ = {0: Fr(1)}
+ZERO_ = {}
+ONE_MINUS_U = {0: Fr(1), 1: Fr(-1)}
+# edge ed traversed counter-clockwise: (xi(u), eta(u)) on this element and on the neighbour
+EDGE_SELF = [(U_, ZERO_), (ONE_, U_), (ONE_MINUS_U, ONE_), (ZERO_, ONE_MINUS_U)]
+EDGE_NB = [(U_, ONE_), (ZERO_, U_), (ONE_MINUS_U, ZERO_), (ONE_, ONE_MINUS_U)]
+EDGE_NB_OFFSET = [(0, -1), (1, 0), (0, 1), (-1, 0)]
+EDGE_VERTS = [(0, 1), (1, 3), (3, 2), (2, 0)]  # local vertices (0,0) (1,0) (0,1) (1,1)
+
+
+def dg_grad(k_poly):
+    return k_poly.dxi(), k_poly.deta()
+
+
+def advect_rate(bm, vx, vy, U, na):
+    """Exact L = M^-1 R of the DG upwind advection rate (reading R14 of the
+    oracle), for v with one sign of v.n along every edge. U[k][e]."""
+    psi = dg_basis(na)
+    norms = [(p * p).integral() for p in psi]
+    out = [[Fr(0)] * bm.ne for _ in range(na)]
+    hx, hy, sh = bm.hx, bm.hy, bm.sh
+    # vertex coordinates of the reference corners (relative): (0,0), (hx,0), (sh,hy), (hx+sh,hy)
+    corner = [(Fr(0), Fr(0)), (hx, Fr(0)), (sh, hy), (hx + sh, hy)]
+    for e in range(bm.ne):
+        ex, ey = e % bm.nx, e // bm.nx
+        ux = sum((bm.phi[a] * vx[bm.node(e, a)] for a in range(9)), Poly())
+        uy = sum((bm.phi[a] * vy[bm.node(e, a)] for a in range(9)), Poly())
+        Ue = sum((psi[k] * U[k][e] for k in range(na)), Poly())
+        R = []
+        for k in range(na):
+            gx, gy = bm.ddx(psi[k]), bm.ddy(psi[k])
+            R.append((Ue * (ux * gx + uy * gy)).integral() * bm.det)
+        for ed in range(4):
+            a0, a1 = EDGE_VERTS[ed]
+            tx = corner[a1][0] - corner[a0][0]
+            ty = corner[a1][1] - corner[a0][1]
+            nlx, nly = ty, -tx
+            xs, es = EDGE_SELF[ed]
+            vn = {}
+            for i, c in restrict(ux, xs, es).items():
+                vn[i] = vn.get(i, Fr(0)) + c * nlx
+            for i, c in restrict(uy, xs, es).items():
+                vn[i] = vn.get(i, Fr(0)) + c * nly
+            sign = upoly_at(vn, Fr(1, 2))
+            fx, fy = ex + EDGE_NB_OFFSET[ed][0], ey + EDGE_NB_OFFSET[ed][1]
+            has_nb = 0 <= fx < bm.nx and 0 <= fy < bm.ny
+            if sign >= 0 or not has_nb:
+                Uup = restrict(Ue, xs, es)
+            else:
+                f = fy * bm.nx + fx
+                Uf = sum((psi[k] * U[k][f] for k in range(na)), Poly())
+                xn, en = EDGE_NB[ed]
+                Uup = restrict(Uf, xn, en)
+            for k in range(na):
+                R[k] -= upoly_int(upoly_mul(vn, Uup, restrict(psi[k], xs, es)))
+        for k in range(na):
+            out[k][e] = R[k] / (norms[k] * bm.det)
+    return out
