@@ -6,9 +6,11 @@ kernel (v^n, lumped masses, air stress) and n_sub = 100 subcycles of strain,
 stress update, divergence and velocity update, with all inputs resident in HBM.
 Prints ONE JSON line:
   value         element-subcycles per second (elements x subcycles x steps / time)
-  roofline      the dominant kernel (the fused subcycle kernel) against the
-                HBM roofline, from its average duration measured with HIP
-                events on the context's stream over the timed region
+  roofline      the dominant kernel (the subcycle kernel of the tuned launch
+                configuration) against the HBM roofline: its algorithmic bytes
+                per launch over its average launch duration, i.e. the HIP-event
+                time of the timed region on the context's stream minus the
+                start-of-step kernels, divided by the number of launches
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
   variants      the same measurement for mixed precision, the larger meshes
                 and the 64-domain batch (one context, one launch per phase)
@@ -68,14 +70,14 @@ def alg_bytes(domains, precision):
     return tot, be, bn
 
 
-def load_traffic(workload, precision, strategy):
+def load_traffic(workload, precision, strategy, tile):
     """HBM traffic per launch of the dominant kernel from committed rocprofv3
     PMC summaries, if they were taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(f"{workload}/{precision}/{strategy}")
+        rec = json.load(open(path)).get(f"{workload}/{precision}/{strategy}/{tile[0]}x{tile[1]}")
     except (ValueError, OSError):
         return None
     if not rec or rec.get("kernel_hash") != kernel_hash():
@@ -83,65 +85,94 @@ def load_traffic(workload, precision, strategy):
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(domains, precision, steps, warmup, n_sub, strategy):
+def run_gpu(domains, precision, steps, warmup, n_sub, strategy=None, tile=None, tune=True):
+    """Upload, optionally autotune (outside the timed region), warm up, then time
+    ``steps`` steps with one event pair around them. Returns the timings and the
+    launch configuration used."""
     import torch
     import paper_2402_00466_amd as M
-    ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in domains], precision=precision,
-                    strategy=strategy)
+    ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in domains], precision=precision)
     for k, d in enumerate(domains):
         ctx.upload(k, d)
     ctx.check_inputs()
+    if strategy is None and tune:
+        ctx.tune(n_trial=max(10, min(n_sub, 50)))
+    elif strategy is not None:
+        ctx.set_config(strategy, tile or (16, 14))
+    config = ctx.get_config()
     for _ in range(warmup):
         ctx.step(n_sub)
-    ctx.timing_enable(steps * n_sub + 8)
+    # start-of-step kernel alone (subtracted from the region to get the subcycle kernels)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ctx.sync()
+    ev[0].record(ctx.stream)
+    for _ in range(3):
+        ctx.begin_step()
+    ev[1].record(ctx.stream)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    begin_ms = ev[0].elapsed_time(ev[1]) / 3
+    # the timed region: `steps` whole steps, events only at its ends
     t0 = time.perf_counter()
-    start.record(ctx.stream)
+    ev[2].record(ctx.stream)
     for _ in range(steps):
         ctx.step(n_sub)
-    stop.record(ctx.stream)
+    ev[3].record(ctx.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = start.elapsed_time(stop)
-    tim = ctx.timing_read()
+    ms = ev[2].elapsed_time(ev[3])
     ctx.check_state()
+    # advection of H and A (once per step before the subcycles; outside the timed region)
+    ev[0].record(ctx.stream)
+    for _ in range(3):
+        ctx.advect()
+    ev[1].record(ctx.stream)
+    torch.cuda.synchronize()
+    advect_ms = ev[0].elapsed_time(ev[1]) / 3
+    # diagnostics outside the timed region: per-launch events over one step
+    ctx.timing_enable(n_sub + 8)
+    ctx.step(n_sub)
+    tim = ctx.timing_read()
+    ctx.timing_enable(0)
     ctx.close()
     del ctx
     torch.cuda.synchronize()
-    return ms, wall, tim
+    return ms, wall, begin_ms, tim, config, advect_ms
 
 
-def measure(domains, precision, steps, warmup, n_sub, workload, strategy="fused"):
-    ms, wall, tim = run_gpu(domains, precision, steps, warmup, n_sub, strategy)
+def measure(domains, precision, steps, warmup, n_sub, workload, strategy=None, tile=None):
+    ms, wall, begin_ms, tim, config, advect_ms = run_gpu(domains, precision, steps, warmup, n_sub,
+                                                         strategy, tile)
+    strategy, tile = config
     el_sub = sum(d.nx * d.ny for d in domains) * n_sub * steps
     value = el_sub / (ms * 1e-3)
     tot, be, bn = alg_bytes(domains, precision)
+    # launches of the subcycle kernel(s) in the timed region
+    if strategy == "persistent":
+        launches, per_launch, kernel = steps, n_sub, "k_fused (persistent: all subcycles of a step)"
+    elif strategy == "two_phase":
+        launches, per_launch, kernel = steps * n_sub, 1, "k_element + k_node (two-phase subcycle)"
+    else:
+        launches, per_launch, kernel = steps * n_sub, 1, "k_fused (one subcycle)"
+    kms = max(ms - steps * begin_ms, 1e-9) / launches  # average launch duration
+    kbytes = tot * per_launch
+    achieved = kbytes / (kms * 1e-3) / 1e9
     c0, t0 = tim["element"]
     c1, t1 = tim["node"]
-    k0 = t0 / max(c0, 1)
-    k1 = t1 / max(c1, 1)
-    if strategy == "fused":
-        kernel, kbytes, kms = "k_subcycle (fused subcycle)", tot, k0
-    else:
-        kernel, kbytes, kms = "k_element (element phase)", be, k0
-    achieved = kbytes / (kms * 1e-3) / 1e9
     return {
         "value": value, "ms_per_step": ms / steps, "wall_s": wall,
-        "kernels_ms": {"subcycle_or_element_avg": k0, "node_avg": k1 if c1 else None,
-                       "begin_step_avg": tim["begin_step"][1] / max(tim["begin_step"][0], 1),
-                       "launches": c0},
+        "config": {"strategy": strategy, "tile": list(tile)},
+        "kernels_ms": {"dominant_avg": kms, "begin_step": begin_ms, "advect_step": advect_ms,
+                       "diag_per_launch_events": {"subcycle_or_element_avg": t0 / max(c0, 1),
+                                                  "node_avg": t1 / c1 if c1 else None,
+                                                  "launches": c0}},
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": load_traffic(workload, precision, strategy),
-                     "alg_bytes_per_launch": kbytes,
-                     "subcycle_alg_GBs": tot / ((k0 + k1) * 1e-3) / 1e9},
+                     "traffic": load_traffic(workload, precision, strategy, tile),
+                     "alg_bytes_per_launch": kbytes, "subcycles_per_launch": per_launch},
     }
 
 
-def traffic_probe(workload, precision, strategy, n_sub, copy_mib):
+def traffic_probe(workload, precision, strategy, tile, n_sub, copy_mib):
     """A short run for hardware-counter collection (rocprofv3 --pmc): a device
     copy of ``copy_mib`` MiB (reads and writes exactly that many bytes; the
     calibration of the byte counters), then one start-of-step kernel and
@@ -157,13 +188,47 @@ def traffic_probe(workload, precision, strategy, n_sub, copy_mib):
     torch.cuda.synchronize()
     del src, dst
     doms = named_workload(workload)
-    ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in doms], precision=precision,
-                    strategy=strategy)
+    ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in doms], precision=precision)
+    ctx.set_config(strategy, tile)
+    ctx.set_graph(False)
     for k, d in enumerate(doms):
         ctx.upload(k, d)
     ctx.step(n_sub)
     ctx.sync()
-    log(f"probe done: copy {copy_mib} MiB x2, {workload} {precision} {strategy} {n_sub} subcycles")
+    log(f"probe done: copy {copy_mib} MiB x2, {workload} {precision} {strategy} {tile} "
+        f"{n_sub} subcycles")
+
+
+def record_traffic(key, fetch_csv, write_csv, copy_mib, kernel_substr, command):
+    """Turn the two rocprofv3 PMC runs of the probe into a traffic record:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the dominant kernel, each
+    scaled by the factor that makes the same counter read exactly ``copy_mib``
+    MiB for the probe's device copy. Stored in profiles/traffic.json under
+    ``key`` with the current kernel-source hash."""
+    import csv
+
+    def rows(path):
+        return list(csv.DictReader(open(path)))
+
+    out = {}
+    for name, path in (("fetch", fetch_csv), ("write", write_csv)):
+        r = rows(path)
+        copies = sorted((float(x["Counter_Value"]) for x in r if "copyBuffer" in x["Kernel_Name"]),
+                        reverse=True)[:2]  # the two copies of copy_mib MiB are the largest
+        kern = [float(x["Counter_Value"]) for x in r if kernel_substr in x["Kernel_Name"]]
+        if len(copies) < 2 or not kern:
+            raise SystemExit(f"{path}: probe copies or kernel {kernel_substr!r} not found")
+        factor = copy_mib * 1024.0 / (sum(copies) / len(copies))
+        out[name] = {"kib_per_dispatch": sum(kern) / len(kern), "dispatches": len(kern),
+                     "copy_kib": sum(copies) / len(copies), "scale": factor}
+    total = (out["fetch"]["kib_per_dispatch"] * out["fetch"]["scale"] +
+             out["write"]["kib_per_dispatch"] * out["write"]["scale"]) * 1024.0
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    db = json.load(open(path)) if os.path.exists(path) else {}
+    db[key] = {"bytes_per_launch": total, "fetch": out["fetch"], "write": out["write"],
+               "kernel": kernel_substr, "kernel_hash": kernel_hash(), "command": command}
+    json.dump(db, open(path, "w"), indent=1, sort_keys=True)
+    print(json.dumps({key: db[key]}))
 
 
 def cpu_baseline(domains, n_sub, budget_s):
@@ -196,14 +261,25 @@ def main():
     ap.add_argument("--n-sub", type=int, default=100)
     ap.add_argument("--workload", default="256x256-dg2")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--strategy", default="fused", choices=["fused", "two_phase"])
+    ap.add_argument("--strategy", default=None, choices=["fused", "two_phase", "persistent"],
+                    help="launch strategy; default: autotuned (mevp_tune) before the timed region")
+    ap.add_argument("--tile", default=None, help="owned tile, e.g. 16x14 (with --strategy)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the short counter-collection probe (see traffic_probe)")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--record-traffic", nargs=3, metavar=("KEY", "FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json[KEY] from the probe's two PMC runs")
+    ap.add_argument("--record-command", default="", help="command line stored with the record")
     args = ap.parse_args()
+    if args.record_traffic:
+        key, fcsv, wcsv = args.record_traffic
+        strategy = key.split("/")[2]
+        record_traffic(key, fcsv, wcsv, args.copy_mib,
+                       "k_element" if strategy == "two_phase" else "k_fused", args.record_command)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the mEVP subcycle "
               "here is single-GPU; see the sharding notes in DESIGN.md", file=sys.stderr)
@@ -217,46 +293,52 @@ def main():
     torch.cuda.set_device(0)
     import paper_2402_00466_amd as M
     M.lib()
+    tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
     if args.traffic_probe:
-        traffic_probe(args.workload, args.precision, args.strategy, args.n_sub if args.n_sub != 100 else 3,
-                      args.copy_mib)
+        traffic_probe(args.workload, args.precision, args.strategy or "fused",
+                      tile or (16, 14), args.n_sub if args.n_sub != 100 else 3, args.copy_mib)
         return
 
     log(f"workload {args.workload} {args.precision}: generating inputs")
     doms = named_workload(args.workload)
     head = measure(doms, args.precision, args.steps, args.warmup, args.n_sub, args.workload,
-                   args.strategy)
-    log(f"headline {head['value']:.3e} element-subcycles/s, {head['ms_per_step']:.3f} ms/step")
+                   args.strategy, tile)
+    log(f"headline {head['value']:.3e} element-subcycles/s, {head['ms_per_step']:.3f} ms/step, "
+        f"{head['config']}, {head['roofline']['frac']:.3f} of HBM peak")
 
     variants = {}
     if not args.no_variants:
         other = "mixed" if args.precision == "fp64" else "fp64"
-        plan = [(args.workload, other, args.steps, args.strategy),
-                (args.workload, args.precision, args.steps, "two_phase"),
-                ("1024x1024-dg2", "fp64", 3, "fused"), ("1024x1024-dg2", "mixed", 3, "fused"),
-                ("2048x2048-dg2", "fp64", 2, "fused"), ("2048x2048-dg2", "mixed", 2, "fused"),
-                ("2048x2048-dg2", "fp64", 2, "two_phase"),
-                ("batch64-dg2", "fp64", 2, "fused"), ("batch64-dg2", "mixed", 2, "fused")]
-        for wl, prec, st, strat in plan:
-            log(f"variant {wl} {prec} {strat} ({st} steps)")
+        plan = [(args.workload, other, args.steps, None, None),
+                (args.workload, args.precision, args.steps, "two_phase", None),
+                (args.workload, args.precision, args.steps, "fused", (16, 14)),
+                (args.workload, args.precision, 3, "persistent", (16, 14)),
+                ("1024x1024-dg2", "fp64", 3, None, None), ("1024x1024-dg2", "mixed", 3, None, None),
+                ("2048x2048-dg2", "fp64", 3, None, None), ("2048x2048-dg2", "mixed", 3, None, None),
+                ("2048x2048-dg2", "fp64", 2, "two_phase", None),
+                ("batch64-dg2", "fp64", 2, None, None), ("batch64-dg2", "mixed", 2, None, None),
+                ("2048x2048-dg2-bilinear", "fp64", 2, None, None),
+                ("2048x2048-dg2-bilinear", "mixed", 2, None, None),
+                ("1024x1024-ns8", "fp64", 2, None, None)]
+        for wl, prec, st, strat, tl in plan:
+            log(f"variant {wl} {prec} {strat or 'tuned'} {tl or ''} ({st} steps)")
             ds = doms if wl == args.workload else named_workload(wl)
-            r = measure(ds, prec, st, 1, args.n_sub, wl, strat)
-            variants[f"{wl}/{prec}/{strat}"] = {
+            r = measure(ds, prec, st, 1, args.n_sub, wl, strat, tl)
+            key = f"{wl}/{prec}/" + (f"{strat}/{tl[0]}x{tl[1]}" if strat and tl else (strat or "tuned"))
+            variants[key] = {
                 "value": r["value"], "ms_per_step": r["ms_per_step"], "steps": st,
-                "elements": sum(d.nx * d.ny for d in ds),
-                "kernel_ms": r["kernels_ms"]["subcycle_or_element_avg"],
-                "node_phase_ms": r["kernels_ms"]["node_avg"],
+                "elements": sum(d.nx * d.ny for d in ds), "config": r["config"],
+                "dominant_kernel_ms": r["kernels_ms"]["dominant_avg"],
                 "roofline_frac": r["roofline"]["frac"],
-                "achieved_GBs": r["roofline"]["achieved"],
-                "subcycle_alg_GBs": r["roofline"]["subcycle_alg_GBs"]}
-            log(f"  {r['value']:.3e} element-subcycles/s, {r['roofline']['kernel']} at "
-                f"{r['roofline']['frac']:.3f} of HBM peak")
+                "achieved_GBs": r["roofline"]["achieved"]}
+            log(f"  {r['value']:.3e} element-subcycles/s ({r['config']['strategy']} "
+                f"{r['config']['tile']}), {r['roofline']['frac']:.3f} of HBM peak")
             del ds
-        mix = variants.get(f"{args.workload}/mixed/{args.strategy}")
-        if mix and args.precision == "fp64":
+        mix = variants.get(f"{args.workload}/mixed/tuned")
+        if mix and args.precision == "fp64" and args.strategy is None:
             variants["mixed_speedup_over_fp64"] = mix["value"] / head["value"]
-        for wl in ("2048x2048-dg2", "batch64-dg2"):
-            a, b = variants.get(f"{wl}/mixed/fused"), variants.get(f"{wl}/fp64/fused")
+        for wl in ("1024x1024-dg2", "2048x2048-dg2", "batch64-dg2"):
+            a, b = variants.get(f"{wl}/mixed/tuned"), variants.get(f"{wl}/fp64/tuned")
             if a and b:
                 variants[f"{wl}/mixed_speedup_over_fp64"] = a["value"] / b["value"]
 
@@ -280,7 +362,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "precision": args.precision,
-                   "strategy": args.strategy,
+                   "strategy": head["config"]["strategy"], "tile": head["config"]["tile"],
                    "domains": len(doms), "elements": sum(d.nx * d.ny for d in doms),
                    "mesh": f"{d0.nx}x{d0.ny}", "n_s": d0.n_s, "n_a": d0.n_a,
                    "n_sub": args.n_sub, "step": "one mEVP time step (start-of-step kernel + n_sub subcycles)"},

@@ -55,7 +55,8 @@ typedef enum {
   MEVP_EDEVICE = -3,      /* HIP error: no device, launch failure, asynchronous fault */
   MEVP_ESTATE = -4,       /* call out of order, e.g. a step before geometry/fields/forcing are set */
   MEVP_ENONFINITE = -5,   /* non-finite or invalid values found by a check call */
-  MEVP_EUNSUPPORTED = -6  /* the current device is not gfx950 */
+  MEVP_EUNSUPPORTED = -6, /* the current device is not gfx950 */
+  MEVP_EINTERNAL = -7     /* a self-check failed (the tuner's bitwise comparison) */
 } mevp_status;
 
 typedef enum {
@@ -70,7 +71,7 @@ typedef enum {
 typedef struct {
   double Pstar;    /* ice strength P* [N m^-2] */
   double C;        /* concentration exponent factor (20 in the listings) */
-  double DeltaMin; /* Delta_min [s^-1], regularises the viscosities */
+  double DeltaMin; /* Delta_min [s^-1], regularises the viscosities, >= 1e-100 */
   double alpha;    /* mEVP stress relaxation, > 0 */
   double beta;     /* mEVP velocity relaxation, >= 0 */
   double rho_i;    /* ice density [kg m^-3] */
@@ -92,18 +93,32 @@ typedef struct {
   int nx, ny, n_s, n_a;
 } mevp_domain_desc;
 
-/* How a subcycle is mapped to launches (both compute the same values; the
- * nodal force sums are taken in the same order, so results agree bitwise).
+/* How subcycles are mapped to launches. All strategies and tile shapes
+ * compute the same values and sum each node's forces in the same order, so
+ * their results agree bitwise.
  * FUSED (default): one launch per subcycle; a workgroup owns a tile of
  * elements and the CG2 nodes at its low edges, recomputes the forces of a
  * one-element halo, keeps all element forces in LDS and updates its nodes;
  * v and S are double-buffered in the workspace.
+ * PERSISTENT: the fused subcycle, with all subcycles of one mevp_subcycles
+ * call in a single cooperative launch (a grid-wide barrier between
+ * subcycles). Used when all domains take the same element kernel; otherwise,
+ * or if the device cannot hold the grid, it falls back to FUSED.
  * TWO_PHASE: an element launch writing the element forces to the workspace,
  * then a node launch gathering them. */
 typedef enum {
   MEVP_STRATEGY_FUSED = 0,
-  MEVP_STRATEGY_TWO_PHASE = 1
+  MEVP_STRATEGY_TWO_PHASE = 1,
+  MEVP_STRATEGY_PERSISTENT = 2
 } mevp_strategy;
+
+/* Launch configuration: strategy and the fused kernel's tile of owned
+ * elements per workgroup (16 x 14; with n_a = 1 also 16 x 16 and 32 x 14). */
+typedef struct {
+  int strategy;  /* a mevp_strategy */
+  int tile_nx;
+  int tile_ny;
+} mevp_config;
 
 typedef struct mevp_ctx mevp_ctx;
 
@@ -128,8 +143,12 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
                         const mevp_domain_desc *domains, int n_domains, void *workspace,
                         size_t ws_bytes, void *hip_stream, mevp_ctx **out);
 
-/* Select how subcycles are launched (default MEVP_STRATEGY_FUSED). */
+/* Select how subcycles are launched (default MEVP_STRATEGY_FUSED, tile
+ * 16 x 14). set_config: EINVAL for an unknown strategy or tile; it waits for
+ * the stream when the tile changes. */
 mevp_status mevp_set_strategy(mevp_ctx *ctx, mevp_strategy strategy);
+mevp_status mevp_set_config(mevp_ctx *ctx, const mevp_config *config);
+mevp_status mevp_get_config(mevp_ctx *ctx, mevp_config *config);
 
 /* Replace the parameters (validated as in mevp_create). */
 mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params);
@@ -148,8 +167,16 @@ mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const dou
 
 /* One time step of every domain (Sec. 2: momentum and mEVP subcycled inside
  * one advection step): mevp_begin_step, then mevp_subcycles(n_subcycles).
- * ESTATE unless geometry, fields and forcing of every domain were set. */
+ * ESTATE unless geometry, fields and forcing of every domain were set.
+ * By default the step's launches are captured once into a HIP graph (per
+ * n_subcycles and state-buffer parity) on a private stream and replayed on
+ * the context's stream; kernel timing, the persistent strategy or a failed
+ * capture launch them one by one instead. Results are identical. */
 mevp_status mevp_step(mevp_ctx *ctx, int n_subcycles);
+
+/* Enable (default) or disable graph replay of mevp_step; drops the captured
+ * graphs. */
+mevp_status mevp_set_graph(mevp_ctx *ctx, int enable);
 
 /* Start a time step: v^n <- v, and per node the lumped ice mass
  * M^H = int rho_i h phi, lumped concentration m^A = int a phi (h, a clamped
@@ -163,6 +190,32 @@ mevp_status mevp_begin_step(mevp_ctx *ctx);
  * lumped-mass velocity update with beta relaxation, air drag, lagged ocean
  * drag and implicit Coriolis; v = 0 on the outer boundary. */
 mevp_status mevp_subcycles(mevp_ctx *ctx, int n);
+
+/* Autotuner: pick the fastest launch configuration for this context's
+ * domains. Runs mevp_begin_step on the current state, then times every
+ * candidate (each strategy; each tile shape available for n_a) on
+ * n_trial >= 1 subcycles from that same state, restoring the state after each
+ * trial, and checks that every candidate reproduces the first one bit for bit
+ * (EINTERNAL if one does not; the previous configuration is kept). Leaves
+ * the state as it was and the winner selected (*chosen, may be NULL).
+ * cache_path (may be NULL): a text file of "key strategy tile_nx tile_ny"
+ * lines, the key naming precision, n_s, n_a and the domain sizes; a matching
+ * line is applied without timing, a new result is appended. Synchronous;
+ * copies the state through host memory. */
+mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_config *chosen);
+
+/* Advect H and A of every domain over one step dt (Sec. 2: the advection
+ * equations Eq. (si:ad) are solved at the large step, before the momentum
+ * subcycles; no sources): DG with the upwind flux, three-stage SSP
+ * Runge-Kutta, the current CG2 velocity held fixed. Per cell, for each DG
+ * test function psi_k: M dU/dt = int_K U v.grad psi_k - sum over edges of
+ * int (v.n) U_up psi_k, U_up the upwind trace (the cell's own trace on the
+ * domain boundary), 3x3 Gauss points in the cell and 3 per edge. Stream-ordered;
+ * no clamping of A (the stress and mass computations clamp h and a). */
+mevp_status mevp_advect(mevp_ctx *ctx);
+
+/* Copy out H and A of domain `dom` ([n_a][ne] each; either may be NULL). */
+mevp_status mevp_get_fields(mevp_ctx *ctx, int dom, double *H, double *A);
 
 /* Copy out the state of domain `dom` (either pointer may be NULL). */
 mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S);

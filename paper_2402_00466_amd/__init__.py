@@ -5,7 +5,7 @@
 device memory and streams.
 """
 from .mevp import (Context, Domain, MevpError, Params, default_params, lib, lib_path,
-                   workspace_size, EXPORTS, FP64, MIXED)
+                   workspace_size, EXPORTS, FP64, MIXED, STRATEGIES, TILES)
 
 __all__ = ["Context", "Domain", "MevpError", "Params", "default_params", "lib", "lib_path",
-           "workspace_size", "EXPORTS", "FP64", "MIXED"]
+           "workspace_size", "EXPORTS", "FP64", "MIXED", "STRATEGIES", "TILES"]

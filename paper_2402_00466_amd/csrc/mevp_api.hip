@@ -5,9 +5,11 @@
 // first element/node) maps for batched launches, and enqueues the kernels of
 // mevp_kernels.hip on the context's stream.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <new>
+#include <string>
 #include <vector>
 
 #include "mevp.h"
@@ -32,6 +34,7 @@ struct mevp_ctx {
   Tile *tiles_d = nullptr;
   int cur = 0;                        // which of the two v / S buffers holds the state
   mevp_strategy strategy = MEVP_STRATEGY_FUSED;
+  int shape = 0;                      // fused-kernel tile shape (index into kTileShapes)
   DevArrays d{};
   DomDev *doms_d = nullptr;
   Blk *eblk_d = nullptr, *nblk_d = nullptr;
@@ -43,6 +46,15 @@ struct mevp_ctx {
     int used = 0;
   } timer[3];
   int timer_cap = 0;
+  // one captured time step per state-buffer parity (hipGraph replay)
+  struct StepGraph {
+    int n = -1;
+    int cur_after = 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+  } graphs[2];
+  hipStream_t cap = nullptr;  // private stream for the captures
+  bool use_graph = true;
 };
 
 namespace {
@@ -60,7 +72,7 @@ mevp_status validate_params(const mevp_params *p) {
                       p->C_a, p->rho_o, p->C_o, p->f_cor, p->dt};
   for (double x : v)
     if (!finite(x)) return MEVP_EINVAL;
-  if (p->Pstar < 0 || p->DeltaMin <= 0 || p->alpha <= 0 || p->beta < 0 || p->dt <= 0 ||
+  if (p->Pstar < 0 || p->DeltaMin < 1e-100 || p->alpha <= 0 || p->beta < 0 || p->dt <= 0 ||
       p->rho_i <= 0 || p->rho_a < 0 || p->C_a < 0 || p->rho_o < 0 || p->C_o < 0)
     return MEVP_EINVAL;
   if (p->relax_form != 0 && p->relax_form != 1) return MEVP_EINVAL;
@@ -90,7 +102,7 @@ KParams derive(const mevp_params &p) {
 
 // Layout of the workspace: offsets in bytes of every array.
 struct Layout {
-  size_t doms, eblk, nblk, tiles, flag, vert, H, A, wind, ocean, v, nc, S, fe, total;
+  size_t doms, eblk, nblk, tiles, flag, vert, H, A, adv, wind, ocean, v, nc, S, fe, total;
   size_t tot_e, tot_n, tot_v;
   int n_eblk, n_nblk;
   int ns, na;
@@ -114,7 +126,13 @@ mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout
     tv += v;
     neb += (e + kElemBlock - 1) / kElemBlock;
     nnb += (n + kNodeBlock - 1) / kNodeBlock;
-    ntl += (long long)((d.nx + kTileEX - 2) / (kTileEX - 1)) * ((d.ny + kTileEY - 2) / (kTileEY - 1));
+    long long most = 0;  // tile table sized for the shape with the most tiles
+    for (int sh = 0; sh < kNumTileShapes; ++sh) {
+      const int tx = kTileShapes[sh][0] - 1, ty = kTileShapes[sh][1] - 1;
+      const long long nt = (long long)((d.nx + tx - 1) / tx) * ((d.ny + ty - 1) / ty);
+      if (nt > most) most = nt;
+    }
+    ntl += most;
     if (te > kIndexMax || tn > kIndexMax || 2 * tn > kIndexMax || 18 * te > (1LL << 40))
       return MEVP_EINVAL;
   }
@@ -133,6 +151,7 @@ mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout
   L->vert = take(sizeof(double) * 2 * tv);
   L->H = take(sizeof(double) * na * te);
   L->A = take(sizeof(double) * na * te);
+  L->adv = take(sizeof(double) * 4 * na * te);
   L->wind = take(sizeof(double) * 2 * tn);
   L->ocean = take(sizeof(double) * 2 * tn);
   L->v = take(sizeof(double) * 4 * tn);
@@ -183,13 +202,21 @@ void timer_stop(mevp_ctx *c, int ph, int slot) {
   if (hipEventRecord(t.ev[2 * slot + 1], c->stream) == hipSuccess) t.used = slot + 1;
 }
 
+void graphs_clear(mevp_ctx *c) {
+  for (auto &g : c->graphs) {
+    if (g.x) (void)hipGraphExecDestroy(g.x);
+    if (g.g) (void)hipGraphDestroy(g.g);
+    g = mevp_ctx::StepGraph{};
+  }
+}
+
 // Element blocks and fused-kernel tiles with the domains of parallelogram
 // cells first (one launch of the constant-Jacobian kernel), then the rest
 // (one launch of the general kernel).
 void order_blocks(mevp_ctx *c) {
   c->eblk_h.clear();
   c->tiles_h.clear();
-  constexpr int TX = kTileEX - 1, TY = kTileEY - 1;
+  const int TX = kTileShapes[c->shape][0] - 1, TY = kTileShapes[c->shape][1] - 1;
   for (int pass = 0; pass < 2; ++pass) {
     for (int i = 0; i < c->nd; ++i) {
       if ((pass == 0) != (c->affine[i] != 0)) continue;
@@ -246,6 +273,7 @@ const char *mevp_status_string(mevp_status s) {
     case MEVP_ESTATE: return "call out of order";
     case MEVP_ENONFINITE: return "non-finite or invalid values";
     case MEVP_EUNSUPPORTED: return "unsupported device";
+    case MEVP_EINTERNAL: return "internal self-check failed";
   }
   return "unknown status";
 }
@@ -350,6 +378,7 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
   d.vert = reinterpret_cast<double *>(base + L.vert);
   d.H = reinterpret_cast<double *>(base + L.H);
   d.A = reinterpret_cast<double *>(base + L.A);
+  d.adv = reinterpret_cast<double *>(base + L.adv);
   d.wind = reinterpret_cast<double *>(base + L.wind);
   d.ocean = reinterpret_cast<double *>(base + L.ocean);
   d.v = reinterpret_cast<double *>(base + L.v);
@@ -381,6 +410,7 @@ mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params) {
   if (st != MEVP_OK) return st;
   ctx->params = *params;
   ctx->kp = derive(*params);
+  graphs_clear(ctx);  // kernel arguments changed
   return MEVP_OK;
 }
 
@@ -399,6 +429,7 @@ mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy) {
   if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(s));
   if (st != MEVP_OK) return st;
   if ((aff != 0) != (ctx->affine[dom] != 0)) {
+    graphs_clear(ctx);  // launch split changes
     ctx->affine[dom] = aff != 0;
     order_blocks(ctx);
     st = copy(ctx->eblk_d, ctx->eblk_h.data(), sizeof(Blk) * ctx->eblk_h.size(), s);
@@ -479,31 +510,65 @@ mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S) {
   return MEVP_OK;
 }
 
-mevp_status mevp_begin_step(mevp_ctx *ctx) {
-  if (!ctx) return MEVP_EINVAL;
+static bool inputs_set(const mevp_ctx *ctx) {
   for (int i = 0; i < ctx->nd; ++i)
-    if (!ctx->geo_set[i] || !ctx->fld_set[i] || !ctx->frc_set[i]) return MEVP_ESTATE;
+    if (!ctx->geo_set[i] || !ctx->fld_set[i] || !ctx->frc_set[i]) return false;
+  return true;
+}
+
+static mevp_status begin_step_on(mevp_ctx *ctx, hipStream_t stream) {
   const int slot = timer_start(ctx, 2);
   mevp_status st = hip_status(launch_begin_step(ctx->d, ctx->kp, ctx->na, ctx->ns,
                                                 v_buf(ctx, ctx->cur), (int)ctx->nblk_h.size(),
-                                                ctx->stream));
+                                                stream));
   timer_stop(ctx, 2, slot);
   return st;
 }
 
-mevp_status mevp_subcycles(mevp_ctx *ctx, int n) {
-  if (!ctx || n < 0) return MEVP_EINVAL;
-  for (int i = 0; i < ctx->nd; ++i)
-    if (!ctx->geo_set[i] || !ctx->fld_set[i] || !ctx->frc_set[i]) return MEVP_ESTATE;
+mevp_status mevp_begin_step(mevp_ctx *ctx) {
+  if (!ctx) return MEVP_EINVAL;
+  if (!inputs_set(ctx)) return MEVP_ESTATE;
+  return begin_step_on(ctx, ctx->stream);
+}
+
+static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
   const bool mixed = ctx->prec == MEVP_MIXED;
+  if (n == 0) return MEVP_OK;
+  // persistent: one cooperative launch for all n subcycles, when every tile
+  // takes the same kernel (all parallelogram domains, or none)
+  if (ctx->strategy == MEVP_STRATEGY_PERSISTENT &&
+      (ctx->tile_split.n_aff == 0 || ctx->tile_split.n_gen == 0)) {
+    const int nxt = ctx->cur ^ 1;
+    FusedArgs f;
+    f.b0 = Bufs{v_buf(ctx, ctx->cur), v_buf(ctx, nxt), S_buf(ctx, ctx->cur), S_buf(ctx, nxt)};
+    f.b1 = Bufs{v_buf(ctx, nxt), v_buf(ctx, ctx->cur), S_buf(ctx, nxt), S_buf(ctx, ctx->cur)};
+    f.shape = ctx->shape;
+    f.persist = 1;
+    f.n_sub = n;
+    const int slot = timer_start(ctx, 0);
+    hipError_t e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->tile_split,
+                                         f, stream);
+    timer_stop(ctx, 0, slot);
+    if (e == hipSuccess) {
+      if (n & 1) ctx->cur = nxt;
+      return MEVP_OK;
+    }
+    if (e != hipErrorCooperativeLaunchTooLarge) return MEVP_EDEVICE;
+    (void)hipGetLastError();  // too many tiles resident per CU: one launch per subcycle
+  }
   for (int it = 0; it < n; ++it) {
     hipError_t e;
-    if (ctx->strategy == MEVP_STRATEGY_FUSED) {
+    if (ctx->strategy != MEVP_STRATEGY_TWO_PHASE) {
       const int nxt = ctx->cur ^ 1;
-      const Bufs b{v_buf(ctx, ctx->cur), v_buf(ctx, nxt), S_buf(ctx, ctx->cur), S_buf(ctx, nxt)};
+      FusedArgs f;
+      f.b0 = Bufs{v_buf(ctx, ctx->cur), v_buf(ctx, nxt), S_buf(ctx, ctx->cur), S_buf(ctx, nxt)};
+      f.b1 = f.b0;
+      f.shape = ctx->shape;
+      f.persist = 0;
+      f.n_sub = 1;
       const int slot = timer_start(ctx, 0);
-      e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->tile_split, b,
-                                ctx->stream);
+      e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->tile_split, f,
+                                stream);
       timer_stop(ctx, 0, slot);
       if (e == hipSuccess) ctx->cur = nxt;
     } else {
@@ -511,11 +576,11 @@ mevp_status mevp_subcycles(mevp_ctx *ctx, int n) {
                    S_buf(ctx, ctx->cur)};
       int slot = timer_start(ctx, 0);
       e = launch_element_phase(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->eblk_split, b,
-                               ctx->stream);
+                               stream);
       timer_stop(ctx, 0, slot);
       if (e == hipSuccess) {
         slot = timer_start(ctx, 1);
-        e = launch_node_phase(ctx->d, ctx->kp, mixed, (int)ctx->nblk_h.size(), b, ctx->stream);
+        e = launch_node_phase(ctx->d, ctx->kp, mixed, (int)ctx->nblk_h.size(), b, stream);
         timer_stop(ctx, 1, slot);
       }
     }
@@ -524,18 +589,141 @@ mevp_status mevp_subcycles(mevp_ctx *ctx, int n) {
   return MEVP_OK;
 }
 
+mevp_status mevp_subcycles(mevp_ctx *ctx, int n) {
+  if (!ctx || n < 0) return MEVP_EINVAL;
+  if (!inputs_set(ctx)) return MEVP_ESTATE;
+  return subcycles_on(ctx, n, ctx->stream);
+}
+
+mevp_status mevp_advect(mevp_ctx *ctx) {
+  if (!ctx) return MEVP_EINVAL;
+  if (!inputs_set(ctx)) return MEVP_ESTATE;
+  // element blocks in any order cover every element of every domain
+  const int nb = (int)ctx->eblk_h.size();
+  const size_t n = (size_t)ctx->na * ctx->tot_e;
+  double *H = const_cast<double *>(ctx->d.H), *A = const_cast<double *>(ctx->d.A);
+  double *H1 = ctx->d.adv, *A1 = H1 + n, *H2 = A1 + n, *A2 = H2 + n;
+  const double *v = v_buf(ctx, ctx->cur), dt = ctx->params.dt;
+  hipStream_t s = ctx->stream;
+  hipError_t e = launch_advect_stage(ctx->d, ctx->na, nb, v, H, A, H, A, H1, A1, dt, 0.0, 1.0, s);
+  if (e == hipSuccess)
+    e = launch_advect_stage(ctx->d, ctx->na, nb, v, H, A, H1, A1, H2, A2, dt, 0.75, 0.25, s);
+  if (e == hipSuccess)
+    e = launch_advect_stage(ctx->d, ctx->na, nb, v, H, A, H2, A2, H, A, dt, 1.0 / 3.0, 2.0 / 3.0, s);
+  return hip_status(e);
+}
+
+mevp_status mevp_get_fields(mevp_ctx *ctx, int dom, double *H, double *A) {
+  if (bad_dom(ctx, dom)) return MEVP_EINVAL;
+  const DomDev &D = ctx->dom_h[dom];
+  const size_t n = (size_t)ctx->na * D.ne, o = (size_t)ctx->na * D.elem_off;
+  mevp_status st = MEVP_OK;
+  if (H) st = copy(H, ctx->d.H + o, sizeof(double) * n, ctx->stream);
+  if (st == MEVP_OK && A) st = copy(A, ctx->d.A + o, sizeof(double) * n, ctx->stream);
+  return st;
+}
+
 mevp_status mevp_set_strategy(mevp_ctx *ctx, mevp_strategy strategy) {
-  if (!ctx || (strategy != MEVP_STRATEGY_FUSED && strategy != MEVP_STRATEGY_TWO_PHASE))
+  if (!ctx) return MEVP_EINVAL;
+  mevp_config c;
+  mevp_get_config(ctx, &c);
+  c.strategy = strategy;
+  return mevp_set_config(ctx, &c);
+}
+
+mevp_status mevp_get_config(mevp_ctx *ctx, mevp_config *out) {
+  if (!ctx || !out) return MEVP_EINVAL;
+  out->strategy = ctx->strategy;
+  out->tile_nx = kTileShapes[ctx->shape][0] - 1;
+  out->tile_ny = kTileShapes[ctx->shape][1] - 1;
+  return MEVP_OK;
+}
+
+mevp_status mevp_set_config(mevp_ctx *ctx, const mevp_config *cfg) {
+  if (!ctx || !cfg) return MEVP_EINVAL;
+  if (cfg->strategy != MEVP_STRATEGY_FUSED && cfg->strategy != MEVP_STRATEGY_TWO_PHASE &&
+      cfg->strategy != MEVP_STRATEGY_PERSISTENT)
     return MEVP_EINVAL;
-  ctx->strategy = strategy;
+  int shape = -1;
+  for (int sh = 0; sh < kNumTileShapes; ++sh)
+    if (kTileShapes[sh][0] - 1 == cfg->tile_nx && kTileShapes[sh][1] - 1 == cfg->tile_ny) shape = sh;
+  if (shape < 0 || (shape != 0 && ctx->na != 1)) return MEVP_EINVAL;  // see kTileShapes
+  ctx->strategy = static_cast<mevp_strategy>(cfg->strategy);
+  graphs_clear(ctx);
+  if (shape != ctx->shape) {
+    ctx->shape = shape;
+    order_blocks(ctx);
+    mevp_status st = copy(ctx->tiles_d, ctx->tiles_h.data(), sizeof(Tile) * ctx->tiles_h.size(), ctx->stream);
+    if (st == MEVP_OK) st = copy(ctx->eblk_d, ctx->eblk_h.data(), sizeof(Blk) * ctx->eblk_h.size(), ctx->stream);
+    // the host tables must outlive the asynchronous copies
+    if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(ctx->stream));
+    return st;
+  }
+  return MEVP_OK;
+}
+
+// Capture begin-step + n subcycles on the private stream into g (nothing runs).
+static mevp_status capture_step(mevp_ctx *ctx, int n, mevp_ctx::StepGraph &g) {
+  if (!ctx->cap && hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking) != hipSuccess) {
+    ctx->cap = nullptr;
+    return MEVP_EDEVICE;
+  }
+  const int cur0 = ctx->cur;
+  if (hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return MEVP_EDEVICE;
+  mevp_status st = begin_step_on(ctx, ctx->cap);
+  if (st == MEVP_OK) st = subcycles_on(ctx, n, ctx->cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+  g.cur_after = ctx->cur;
+  ctx->cur = cur0;  // the capture ran nothing
+  if (st != MEVP_OK || e != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return MEVP_EDEVICE;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return MEVP_EDEVICE;
+  }
+  g.g = graph;
+  g.x = exec;
+  g.n = n;
   return MEVP_OK;
 }
 
 mevp_status mevp_step(mevp_ctx *ctx, int n_subcycles) {
   if (!ctx || n_subcycles < 0) return MEVP_EINVAL;
-  mevp_status st = mevp_begin_step(ctx);
+  if (!inputs_set(ctx)) return MEVP_ESTATE;
+  // replay a captured step when nothing needs per-launch events; cooperative
+  // launches are not captured
+  if (ctx->use_graph && ctx->timer_cap == 0 && ctx->strategy != MEVP_STRATEGY_PERSISTENT) {
+    mevp_ctx::StepGraph &g = ctx->graphs[ctx->cur];
+    if (g.x && g.n != n_subcycles) {
+      (void)hipGraphExecDestroy(g.x);
+      (void)hipGraphDestroy(g.g);
+      g = mevp_ctx::StepGraph{};
+    }
+    if (!g.x && capture_step(ctx, n_subcycles, g) != MEVP_OK) {
+      ctx->use_graph = false;  // capture unsupported here: launch eagerly from now on
+    } else if (g.x) {
+      if (hipGraphLaunch(g.x, ctx->stream) != hipSuccess) return MEVP_EDEVICE;
+      ctx->cur = g.cur_after;
+      return MEVP_OK;
+    }
+  }
+  mevp_status st = begin_step_on(ctx, ctx->stream);
   if (st != MEVP_OK) return st;
-  return mevp_subcycles(ctx, n_subcycles);
+  return subcycles_on(ctx, n_subcycles, ctx->stream);
+}
+
+mevp_status mevp_set_graph(mevp_ctx *ctx, int enable) {
+  if (!ctx) return MEVP_EINVAL;
+  graphs_clear(ctx);
+  ctx->use_graph = enable != 0;
+  return MEVP_OK;
 }
 
 mevp_status mevp_sync(mevp_ctx *ctx) {
@@ -621,8 +809,137 @@ mevp_status mevp_timing_read(mevp_ctx *ctx, int *count, double *total_ms) {
   return MEVP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+static std::string tune_key(const mevp_ctx *c) {
+  long long ne = 0, mx = 0, my = 0;
+  for (const auto &d : c->desc) {
+    ne += (long long)d.nx * d.ny;
+    if (d.nx > mx) mx = d.nx;
+    if (d.ny > my) my = d.ny;
+  }
+  char buf[160];
+  snprintf(buf, sizeof buf, "gfx950/%s/ns%d/na%d/dom%d/el%lld/max%lldx%lld",
+           c->prec == MEVP_MIXED ? "mixed" : "fp64", c->ns, c->na, c->nd, ne, mx, my);
+  return buf;
+}
+
+static bool cache_lookup(const char *path, const std::string &key, mevp_config *cfg) {
+  FILE *f = path ? fopen(path, "r") : nullptr;
+  if (!f) return false;
+  char line[512], k[256];
+  bool hit = false;
+  while (fgets(line, sizeof line, f)) {
+    mevp_config c;
+    if (sscanf(line, "%255s %d %d %d", k, &c.strategy, &c.tile_nx, &c.tile_ny) == 4 && key == k) {
+      *cfg = c;  // the last matching line wins
+      hit = true;
+    }
+  }
+  fclose(f);
+  return hit;
+}
+
+static mevp_status save_state(mevp_ctx *c, std::vector<char> &buf) {
+  const size_t vb = sizeof(double) * 2 * c->tot_n, sb = s_words(c) * s_bytes(c);
+  buf.resize(vb + sb);
+  mevp_status st = hip_status(hipMemcpyAsync(buf.data(), v_buf(c, c->cur), vb, hipMemcpyDeviceToHost, c->stream));
+  if (st == MEVP_OK)
+    st = hip_status(hipMemcpyAsync(buf.data() + vb, S_buf(c, c->cur), sb, hipMemcpyDeviceToHost, c->stream));
+  if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(c->stream));
+  return st;
+}
+
+static mevp_status restore_state(mevp_ctx *c, const std::vector<char> &buf) {
+  const size_t vb = sizeof(double) * 2 * c->tot_n, sb = s_words(c) * s_bytes(c);
+  mevp_status st = hip_status(hipMemcpyAsync(v_buf(c, c->cur), buf.data(), vb, hipMemcpyHostToDevice, c->stream));
+  if (st == MEVP_OK)
+    st = hip_status(hipMemcpyAsync(S_buf(c, c->cur), buf.data() + vb, sb, hipMemcpyHostToDevice, c->stream));
+  if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(c->stream));
+  return st;
+}
+
+mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_config *chosen) {
+  if (!ctx || n_trial < 1 || n_trial > 100000) return MEVP_EINVAL;
+  if (!inputs_set(ctx)) return MEVP_ESTATE;
+  const std::string key = tune_key(ctx);
+  mevp_config cfg;
+  if (cache_lookup(cache_path, key, &cfg) && mevp_set_config(ctx, &cfg) == MEVP_OK) {
+    if (chosen) *chosen = cfg;
+    return MEVP_OK;
+  }
+  std::vector<mevp_config> cand;
+  for (int sh = 0; sh < kNumTileShapes; ++sh) {
+    if (sh != 0 && ctx->na != 1) continue;
+    cand.push_back(mevp_config{MEVP_STRATEGY_FUSED, kTileShapes[sh][0] - 1, kTileShapes[sh][1] - 1});
+  }
+  cand.push_back(mevp_config{MEVP_STRATEGY_TWO_PHASE, kTileShapes[0][0] - 1, kTileShapes[0][1] - 1});
+  cand.push_back(mevp_config{MEVP_STRATEGY_PERSISTENT, kTileShapes[0][0] - 1, kTileShapes[0][1] - 1});
+
+  mevp_config before;
+  mevp_get_config(ctx, &before);
+  const int timer_cap = ctx->timer_cap;
+  ctx->timer_cap = 0;  // no per-launch events inside the trials
+  mevp_status st = begin_step_on(ctx, ctx->stream);
+  std::vector<char> saved, ref, got;
+  if (st == MEVP_OK) st = save_state(ctx, saved);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (st == MEVP_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    st = MEVP_EDEVICE;
+  float best = 0.f;
+  int best_i = -1;
+  const int cur0 = ctx->cur;
+  for (size_t i = 0; i < cand.size() && st == MEVP_OK; ++i) {
+    st = mevp_set_config(ctx, &cand[i]);
+    if (st != MEVP_OK) break;
+    // warm-up trial (first-use costs), then the timed one, both from the saved state
+    for (int rep = 0; rep < 2 && st == MEVP_OK; ++rep) {
+      ctx->cur = cur0;
+      st = restore_state(ctx, saved);
+      if (st != MEVP_OK) break;
+      if (rep == 1) st = hip_status(hipEventRecord(e0, ctx->stream));
+      if (st == MEVP_OK) st = subcycles_on(ctx, n_trial, ctx->stream);
+      if (st == MEVP_OK && rep == 1) st = hip_status(hipEventRecord(e1, ctx->stream));
+      if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(ctx->stream));
+    }
+    float ms = 0.f;
+    if (st == MEVP_OK) st = hip_status(hipEventElapsedTime(&ms, e0, e1));
+    // every configuration must reproduce the first one bit for bit
+    if (st == MEVP_OK) st = save_state(ctx, i == 0 ? ref : got);
+    if (st == MEVP_OK && i > 0 && (got.size() != ref.size() || memcmp(got.data(), ref.data(), ref.size()) != 0))
+      st = MEVP_EINTERNAL;
+    if (st == MEVP_OK && (best_i < 0 || ms < best)) {
+      best = ms;
+      best_i = (int)i;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  // leave the state as it was, with the winner (or the previous config on error)
+  ctx->cur = cur0;
+  mevp_status rs = saved.empty() ? MEVP_OK : restore_state(ctx, saved);
+  ctx->timer_cap = timer_cap;
+  mevp_status cs = mevp_set_config(ctx, st == MEVP_OK ? &cand[best_i] : &before);
+  if (st != MEVP_OK) return st;
+  if (rs != MEVP_OK) return rs;
+  if (cs != MEVP_OK) return cs;
+  if (chosen) *chosen = cand[best_i];
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%s %d %d %d\n", key.c_str(), cand[best_i].strategy, cand[best_i].tile_nx,
+              cand[best_i].tile_ny);
+      fclose(f);
+    }
+  }
+  return MEVP_OK;
+}
+
 void mevp_destroy(mevp_ctx *ctx) {
   if (!ctx) return;
+  graphs_clear(ctx);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   timer_free(ctx);
   delete ctx;
 }

@@ -1,0 +1,1112 @@
+#pragma once
+// mevp_device.hpp -- gfx950 device code of the mEVP momentum subcycle (included by
+// the per-n_s kernel translation units and mevp_kernels.hip).
+//
+// One subcycle (Table 1 of the paper: strain, stress, divergence, velocity)
+// is two launches:
+//   element phase  one element per lane: gather the 9 CG2 velocities, strain
+//                  rates, L2 projection onto the DG stress space, the VP stress
+//                  update of Listing 1 (S read and written once), the new
+//                  stress and the weak-form nodal forces of the element
+//                  (18 values, written to a scratch array, element-fastest).
+//                  Two kernels: parallelogram cells (constant Jacobian,
+//                  diagonal mass matrix, strain and divergence as exact
+//                  constant operators) and general bilinear cells (Jacobian
+//                  per Gauss point, local mass matrix factorised per element).
+//   node phase     one CG2 node per lane: sum the forces of the <= 4 elements
+//                  around the node in ascending element order (deterministic,
+//                  no atomics), then the lumped-mass velocity update.
+// The element maps are recomputed from the cell vertices in every subcycle
+// (the paper's "on-the-fly map", Sec. 3.2) instead of being stored.
+//
+// Arrays are element- or node-fastest (structure of arrays), so consecutive
+// lanes touch consecutive addresses for S, H, A, the forces and the node
+// arrays; the 3x3 velocity gather of neighbouring elements overlaps and is
+// served from L2.
+#include <hip/hip_cooperative_groups.h>
+
+#include "mevp_internal.hpp"
+#include "mevp_ref.hpp"
+
+namespace mevp {
+namespace {
+
+// Bilinear cell map from the vertices (0,0), (1,0), (0,1), (1,1) of the
+// reference square: J(xi, eta) = [[J00, J01], [J10, J11]] with
+//   J00 = (1-eta) ax + eta bx, J01 = (1-xi) cx + xi dx, and the same in y.
+template <class T>
+struct Cell {
+  T ax, bx, cx, dx, ay, by, cy, dy;
+  __device__ __forceinline__ void jac(double xi, double eta, T &J00, T &J01, T &J10,
+                                      T &J11) const {
+    J00 = T(1.0 - eta) * ax + T(eta) * bx;
+    J01 = T(1.0 - xi) * cx + T(xi) * dx;
+    J10 = T(1.0 - eta) * ay + T(eta) * by;
+    J11 = T(1.0 - xi) * cy + T(xi) * dy;
+  }
+};
+
+template <class T>
+__device__ __forceinline__ Cell<T> load_cell(const DomDev &D, const double *vert, int ex, int ey) {
+  const double *VX = vert + 2 * (size_t)D.vert_off;
+  const double *VY = VX + D.nv;
+  const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
+  const double X0 = VX[i0], X1 = VX[i0 + 1], X2 = VX[i2], X3 = VX[i2 + 1];
+  const double Y0 = VY[i0], Y1 = VY[i0 + 1], Y2 = VY[i2], Y3 = VY[i2 + 1];
+  Cell<T> c;
+  c.ax = T(X1 - X0);
+  c.bx = T(X3 - X2);
+  c.cx = T(X2 - X0);
+  c.dx = T(X3 - X1);
+  c.ay = T(Y1 - Y0);
+  c.by = T(Y3 - Y2);
+  c.cy = T(Y2 - Y0);
+  c.dy = T(Y3 - Y1);
+  return c;
+}
+
+// Local mass matrix M_e = Psi W_e Psi^T (W_e = diag(w_q |J_q|)) factorised as
+// L D L^T with unit lower L; solve() applies M_e^-1 in place.
+template <int NS, class T>
+struct Ldl {
+  T L[NS][NS];
+  T invd[NS];
+  template <class Q>
+  __device__ __forceinline__ void build(const Cell<T> &c) {
+    T M[NS][NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+      for (int l = 0; l <= k; ++l) M[k][l] = T(0);
+#pragma unroll
+    for (int q = 0; q < Q::NG; ++q) {
+      T J00, J01, J10, J11;
+      c.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+      const T wd = T(Q::w(q)) * (J00 * J11 - J01 * J10);
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int l = 0; l <= k; ++l) {
+          const double pp = Q::psi(k, q) * Q::psi(l, q);
+          if (pp != 0.0) M[k][l] += T(pp) * wd;
+        }
+    }
+    T dv[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      T dj = M[j][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k] * dv[k];
+      dv[j] = dj;
+      invd[j] = T(1) / dj;
+#pragma unroll
+      for (int i = j + 1; i < NS; ++i) {
+        T s = M[i][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k] * dv[k];
+        L[i][j] = s * invd[j];
+      }
+    }
+  }
+  __device__ __forceinline__ void solve(T (&x)[NS]) const {
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+#pragma unroll
+      for (int k = 0; k < i; ++k) x[i] -= L[i][k] * x[k];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) x[i] *= invd[i];
+#pragma unroll
+    for (int i = NS - 1; i >= 0; --i)
+#pragma unroll
+      for (int k = i + 1; k < NS; ++k) x[i] -= L[k][i] * x[k];
+  }
+};
+
+// Ice strength at Gauss point q: P = P* max(0, H Psi) exp(-C (1 - min(1, max(0, A Psi))))
+// (clamps and formula of the stress listings), always in double.
+template <int NA, class Q>
+__device__ __forceinline__ double ice_strength(const KParams &p, const double (&Hc)[NA],
+                                               const double (&Ac)[NA], int q) {
+  double hs = 0.0, as = 0.0;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    hs += Hc[k] * Q::psi(k, q);
+    as += Ac[k] * Q::psi(k, q);
+  }
+  const double h = fmax(0.0, hs);
+  const double a = fmin(1.0, fmax(0.0, as));
+  return p.Pstar * h * exp(-p.C * (1.0 - a));
+}
+
+// 1/sqrt(x) for a normal x > 0: the hardware estimate refined by two Newton
+// steps y <- y + y (1 - x y^2) / 2, each doubling the number of correct bits.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-(x * y), y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-(x * y), y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// VP stress at one Gauss point (Listing 1): Delta and P/Delta in double,
+// s11 = P/Delta (5/8 e11 + 3/8 e22) - P/2, s12 = P/Delta e12 / 4, s22 alike.
+template <class T>
+__device__ __forceinline__ void vp_stress(const KParams &p, double P, T e11, T e12, T e22, T &s11,
+                                          T &s12, T &s22) {
+  const double de11 = e11, de12 = e12, de22 = e22;
+  const double D2 = p.dmin2 + 1.25 * (de11 * de11 + de22 * de22) + 1.5 * de11 * de22 + de12 * de12;
+  const double PD = P * rsqrt_nr(D2);  // D2 >= Delta_min^2, a normal double
+  const T tPD = T(PD), thP = T(0.5 * P);
+  s11 = tPD * (T(0.625) * e11 + T(0.375) * e22) - thP;
+  s12 = tPD * T(0.25) * e12;
+  s22 = tPD * (T(0.625) * e22 + T(0.375) * e11) - thP;
+}
+
+// Velocities of the 9 local nodes of element (ex, ey). In float they are
+// taken relative to local node 0 before narrowing (the gradient of a constant
+// is zero), which keeps the strain free of cancellation.
+template <class T>
+__device__ __forceinline__ void load_velocity(const DomDev &D, const double *v, int ex, int ey,
+                                              T (&vx)[9], T (&vy)[9]) {
+  const double *vxg = v + 2 * (size_t)D.node_off;
+  const double *vyg = vxg + D.nn;
+  const int NX = 2 * D.nx + 1;
+  const int j0 = 2 * ey * NX + 2 * ex;
+  double bx = 0.0, by = 0.0;
+  if (sizeof(T) < sizeof(double)) {
+    bx = vxg[j0];
+    by = vyg[j0];
+  }
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int j = j0 + b * NX + c;
+      vx[3 * b + c] = T(vxg[j] - bx);
+      vy[3 * b + c] = T(vyg[j] - by);
+    }
+}
+
+template <int NA>
+__device__ __forceinline__ void load_ice(const DevArrays &d, const DomDev &D, int el,
+                                         double (&Hc)[NA], double (&Ac)[NA]) {
+  const size_t ne = (size_t)D.ne;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    Hc[k] = d.H[((size_t)NA * D.elem_off) + k * ne + el];
+    Ac[k] = d.A[((size_t)NA * D.elem_off) + k * ne + el];
+  }
+}
+
+// Relaxation of Listing 1: R <- fac S_in + ainv R (R holds Pi_e(s) on entry).
+template <int NS, class T, class TS>
+__device__ __forceinline__ void relax(const TS *S_in, size_t ne, int el, const KParams &p,
+                                      T (&R11)[NS], T (&R12)[NS], T (&R22)[NS]) {
+  const T fac = T(p.fac), ainv = T(p.ainv);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    R11[k] = fac * T(S_in[(0 * NS + k) * ne + el]) + ainv * R11[k];
+    R12[k] = fac * T(S_in[(1 * NS + k) * ne + el]) + ainv * R12[k];
+    R22[k] = fac * T(S_in[(2 * NS + k) * ne + el]) + ainv * R22[k];
+  }
+}
+
+template <int NS, class T, class TS>
+__device__ __forceinline__ void store_stress(TS *S_out, size_t ne, int el, const T (&R11)[NS],
+                                             const T (&R12)[NS], const T (&R22)[NS]) {
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    S_out[(0 * NS + k) * ne + el] = TS(R11[k]);
+    S_out[(1 * NS + k) * ne + el] = TS(R12[k]);
+    S_out[(2 * NS + k) * ne + el] = TS(R22[k]);
+  }
+}
+
+// Per-domain base pointers of the buffers a subcycle reads and writes.
+template <class TS>
+struct DomBufs {
+  const double *v_in;
+  double *v_out;
+  const TS *S_in;
+  TS *S_out;
+  __device__ __forceinline__ DomBufs(const Bufs &b, const DomDev &D, int ns) {
+    v_in = b.v_in + 2 * (size_t)D.node_off;
+    v_out = b.v_out + 2 * (size_t)D.node_off;
+    S_in = static_cast<const TS *>(b.S_in) + (size_t)3 * ns * D.elem_off;
+    S_out = static_cast<TS *>(b.S_out) + (size_t)3 * ns * D.elem_off;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Element update, parallelogram cells: strain -> stress update -> nodal forces.
+// J = [[J00, J01], [J10, J11]] is constant, |J| cancels from the projections
+// (M_e = |J| diag(int psi_k^2)), and
+//   w|J| grad v projected:  R11[k] = J11 (Axi vx)[k] - J10 (Aeta vx)[k], ...
+//   divergence:            f_x[a] = -(J11 (Axi^T S11)[a] - J01 (Axi^T S12)[a]
+//                                     + J00 (Aeta^T S12)[a] - J10 (Aeta^T S11)[a])
+// with the exact reference operators a_xi, a_eta of mevp_ref.hpp.
+// On return R holds the new stress coefficients and fx, fy the forces.
+// ---------------------------------------------------------------------------
+template <int NS, int NA, class T, class TS>
+__device__ __forceinline__ void element_affine(const DevArrays &d, const DomDev &D,
+                                               const KParams &p, const double *v_in,
+                                               const TS *S_in, int el, int ex, int ey,
+                                               T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
+                                               T (&fx)[9], T (&fy)[9]) {
+  using Q = Quad<Ngp<NS>::value>;
+  constexpr int NG = Q::NG;
+  T J00, J01, J10, J11;
+  {
+    const double *VX = d.vert + 2 * (size_t)D.vert_off;
+    const double *VY = VX + D.nv;
+    const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
+    const double X0 = VX[i0], Y0 = VY[i0];
+    J00 = T(VX[i0 + 1] - X0);
+    J10 = T(VY[i0 + 1] - Y0);
+    J01 = T(VX[i2] - X0);
+    J11 = T(VY[i2] - Y0);
+  }
+  const T idet = T(1) / (J00 * J11 - J01 * J10);
+
+  // ---- strain ----
+  T vx[9], vy[9];
+  load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
+  T E11[NS], E12[NS], E22[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    T gxx = 0, gxe = 0, gyx = 0, gye = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      if (a_xi(k, a) != 0.0) {
+        gxx += T(a_xi(k, a)) * vx[a];
+        gyx += T(a_xi(k, a)) * vy[a];
+      }
+      if (a_eta(k, a) != 0.0) {
+        gxe += T(a_eta(k, a)) * vx[a];
+        gye += T(a_eta(k, a)) * vy[a];
+      }
+    }
+    const T sc = idet * T(1.0 / dg_mass(k));
+    E11[k] = (J11 * gxx - J10 * gxe) * sc;
+    E22[k] = (J00 * gye - J01 * gyx) * sc;
+    E12[k] = T(0.5) * ((J00 * gxe - J01 * gxx) + (J11 * gyx - J10 * gye)) * sc;
+  }
+
+  // ---- stress update ----
+  double Hc[NA], Ac[NA];
+  load_ice<NA>(d, D, el, Hc, Ac);
+  const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    T e11 = 0, e12 = 0, e22 = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (Q::psi(k, q) != 0.0) {
+        const T ps = T(Q::psi(k, q));
+        e11 += E11[k] * ps;
+        e12 += E12[k] * ps;
+        e22 += E22[k] * ps;
+      }
+    }
+    const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
+    T s11, s12, s22;
+    vp_stress<T>(p, P, e11, e12, e22, s11, s12, s22);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (Q::psi(k, q) != 0.0) {
+        const T pw = T(Q::w(q) * Q::psi(k, q) / dg_mass(k));
+        R11[k] += pw * s11;
+        R12[k] += pw * s12;
+        R22[k] += pw * s22;
+      }
+    }
+  }
+  relax<NS, T, TS>(S_in, (size_t)D.ne, el, p, R11, R12, R22);
+
+  // ---- divergence, element part ----
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    T bx11 = 0, be11 = 0, bx12 = 0, be12 = 0, bx22 = 0, be22 = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (a_xi(k, a) != 0.0) {
+        const T c = T(a_xi(k, a));
+        bx11 += c * R11[k];
+        bx12 += c * R12[k];
+        bx22 += c * R22[k];
+      }
+      if (a_eta(k, a) != 0.0) {
+        const T c = T(a_eta(k, a));
+        be11 += c * R11[k];
+        be12 += c * R12[k];
+        be22 += c * R22[k];
+      }
+    }
+    fx[a] = -((J11 * bx11 - J01 * bx12) + (J00 * be12 - J10 * be11));
+    fy[a] = -((J11 * bx12 - J01 * bx22) + (J00 * be22 - J10 * be12));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Element update, general bilinear cells: Jacobian per Gauss point, local
+// mass matrix M_e = Psi W_e Psi^T factorised per element.
+// ---------------------------------------------------------------------------
+template <int NS, int NA, class T, class TS>
+__device__ __forceinline__ void element_general(const DevArrays &d, const DomDev &D,
+                                                const KParams &p, const double *v_in,
+                                                const TS *S_in, int el, int ex, int ey,
+                                                T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
+                                                T (&fx)[9], T (&fy)[9]) {
+  using Q = Quad<Ngp<NS>::value>;
+  constexpr int NG = Q::NG;
+  const Cell<T> cell = load_cell<T>(D, d.vert, ex, ey);
+  Ldl<NS, T> mass;
+  mass.template build<Q>(cell);
+
+  // ---- strain ----
+  T vx[9], vy[9];
+  load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
+  T E11[NS], E12[NS], E22[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) E11[k] = E12[k] = E22[k] = T(0);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    T gxx = 0, gxe = 0, gyx = 0, gye = 0;  // d/dxi and d/deta of vx, vy
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      if (Q::dxi(a, q) != 0.0) {
+        gxx += T(Q::dxi(a, q)) * vx[a];
+        gyx += T(Q::dxi(a, q)) * vy[a];
+      }
+      if (Q::deta(a, q) != 0.0) {
+        gxe += T(Q::deta(a, q)) * vx[a];
+        gye += T(Q::deta(a, q)) * vy[a];
+      }
+    }
+    T J00, J01, J10, J11;
+    cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+    // w_q |J_q| grad v = w_q adj(J)^T (d/dxi, d/deta) v: the determinant cancels
+    const T w = T(Q::w(q));
+    const T e11 = w * (J11 * gxx - J10 * gxe);
+    const T e22 = w * (J00 * gye - J01 * gyx);
+    const T e12 = T(0.5) * w * ((J00 * gxe - J01 * gxx) + (J11 * gyx - J10 * gye));
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (Q::psi(k, q) != 0.0) {
+        const T ps = T(Q::psi(k, q));
+        E11[k] += ps * e11;
+        E12[k] += ps * e12;
+        E22[k] += ps * e22;
+      }
+    }
+  }
+  mass.solve(E11);
+  mass.solve(E12);
+  mass.solve(E22);
+
+  // ---- stress update ----
+  double Hc[NA], Ac[NA];
+  load_ice<NA>(d, D, el, Hc, Ac);
+  const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    T e11 = 0, e12 = 0, e22 = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (Q::psi(k, q) != 0.0) {
+        const T ps = T(Q::psi(k, q));
+        e11 += E11[k] * ps;
+        e12 += E12[k] * ps;
+        e22 += E22[k] * ps;
+      }
+    }
+    const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
+    T s11, s12, s22;
+    vp_stress<T>(p, P, e11, e12, e22, s11, s12, s22);
+    T J00, J01, J10, J11;
+    cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+    const T wd = T(Q::w(q)) * (J00 * J11 - J01 * J10);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (Q::psi(k, q) != 0.0) {
+        const T pw = T(Q::psi(k, q)) * wd;
+        R11[k] += pw * s11;
+        R12[k] += pw * s12;
+        R22[k] += pw * s22;
+      }
+    }
+  }
+  mass.solve(R11);
+  mass.solve(R12);
+  mass.solve(R22);
+  relax<NS, T, TS>(S_in, (size_t)D.ne, el, p, R11, R12, R22);
+
+  // ---- divergence, element part: f[a] = -sum_q w_q |J_q| sigma(q) grad phi_a(q)
+  //      = -sum_q (dphi_a/dxi Gxi + dphi_a/deta Geta) with G = w_q sigma adj(J)^T ----
+#pragma unroll
+  for (int a = 0; a < 9; ++a) fx[a] = fy[a] = T(0);
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    T s11 = 0, s12 = 0, s22 = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      if (Q::psi(k, q) != 0.0) {
+        const T ps = T(Q::psi(k, q));
+        s11 += R11[k] * ps;
+        s12 += R12[k] * ps;
+        s22 += R22[k] * ps;
+      }
+    }
+    T J00, J01, J10, J11;
+    cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+    const T w = T(Q::w(q));
+    const T gxxi = w * (s11 * J11 - s12 * J01);
+    const T gxet = w * (s12 * J00 - s11 * J10);
+    const T gyxi = w * (s12 * J11 - s22 * J01);
+    const T gyet = w * (s22 * J00 - s12 * J10);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      if (Q::dxi(a, q) != 0.0) {
+        fx[a] -= T(Q::dxi(a, q)) * gxxi;
+        fy[a] -= T(Q::dxi(a, q)) * gyxi;
+      }
+      if (Q::deta(a, q) != 0.0) {
+        fx[a] -= T(Q::deta(a, q)) * gxet;
+        fy[a] -= T(Q::deta(a, q)) * gyet;
+      }
+    }
+  }
+}
+
+template <int NS, int NA, class T, class TS, bool AFF>
+__device__ __forceinline__ void element_update(const DevArrays &d, const DomDev &D,
+                                               const KParams &p, const double *v_in,
+                                               const TS *S_in, int el, int ex, int ey,
+                                               T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
+                                               T (&fx)[9], T (&fy)[9]) {
+  if constexpr (AFF)
+    element_affine<NS, NA, T, TS>(d, D, p, v_in, S_in, el, ex, ey, R11, R12, R22, fx, fy);
+  else
+    element_general<NS, NA, T, TS>(d, D, p, v_in, S_in, el, ex, ey, R11, R12, R22, fx, fy);
+}
+
+// Velocity update of one interior node:
+//   (c (1+beta) + d) v + b k x v = c beta v^{p-1} + g + d v_o + F
+// with c = M^H/dt, b = f M^H, d = m^A rho_o C_o |v_o - v^{p-1}| and
+// g = c v^n + m^A tau_a (node constants nc[6][nn] of the step), closed form.
+__device__ __forceinline__ void velocity_update6(const KParams &p, const double (&o)[6], double ux,
+                                                 double uy, double Fx, double Fy, double &vx,
+                                                 double &vy);
+__device__ __forceinline__ void velocity_update(const KParams &p, const double *nc, size_t nn,
+                                                int j, double ux, double uy, double Fx,
+                                                double Fy, double &vx, double &vy) {
+  const double o[6] = {nc[j], nc[nn + j], nc[2 * nn + j], nc[3 * nn + j], nc[4 * nn + j],
+                       nc[5 * nn + j]};
+  velocity_update6(p, o, ux, uy, Fx, Fy, vx, vy);
+}
+
+// velocity_update with the six node constants already loaded
+__device__ __forceinline__ void velocity_update6(const KParams &p, const double (&o)[6], double ux,
+                                                 double uy, double Fx, double Fy, double &vx,
+                                                 double &vy) {
+  const double c = o[0], ko = o[1], gx = o[2], gy = o[3], ox = o[4], oy = o[5];
+  const double dox = ox - ux, doy = oy - uy;
+  const double dd = ko * sqrt(dox * dox + doy * doy);
+  const double bb = c * p.f_dt;
+  const double cb = c * p.beta;
+  const double rx = cb * ux + gx + dd * ox + Fx;
+  const double ry = cb * uy + gy + dd * oy + Fy;
+  const double aa = c * (1.0 + p.beta) + dd;
+  const double den = aa * aa + bb * bb;
+  if (den == 0.0) {
+    vx = 0.0;
+    vy = 0.0;
+  } else {
+    const double inv = 1.0 / den;
+    vx = (aa * rx + bb * ry) * inv;
+    vy = (aa * ry - bb * rx) * inv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-phase subcycle, element kernel: element update, S written in place
+// (each lane reads and writes only its own element), forces to scratch.
+// ---------------------------------------------------------------------------
+template <int NS, int NA, class T, class TS, bool AFF>
+__global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p, const Blk *blks,
+                                                        Bufs b) {
+  const Blk blk = blks[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int el = blk.first + (int)threadIdx.x;
+  if (el >= D.ne) return;
+  const int ex = el % D.nx, ey = el / D.nx;
+  const DomBufs<TS> B(b, D, NS);
+  T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
+  element_update<NS, NA, T, TS, AFF>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx, fy);
+  store_stress<NS, T, TS>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
+  const size_t ne = (size_t)D.ne;
+  TS *fe = static_cast<TS *>(d.fe) + (size_t)18 * D.elem_off;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    fe[a * ne + el] = TS(fx[a]);
+    fe[(9 + a) * ne + el] = TS(fy[a]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Two-phase subcycle, node kernel: deterministic gather of the element forces
+// (ascending element order, no atomics) + velocity update, v in place.
+// ---------------------------------------------------------------------------
+template <class TF>
+__global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p, Bufs b) {
+  const Blk blk = d.nblk[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int j = blk.first + (int)threadIdx.x;
+  if (j >= D.nn) return;
+  const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
+  const int ix = j % NX, iy = j / NX;
+  const double *vin = b.v_in + 2 * (size_t)D.node_off;
+  double *vout = b.v_out + 2 * (size_t)D.node_off;
+  if (ix == 0 || iy == 0 || ix == NX - 1 || iy == NY - 1) {
+    vout[j] = 0.0;
+    vout[D.nn + j] = 0.0;
+    return;
+  }
+  // elements around node (ix, iy): for an odd index the one element whose
+  // middle node it is, for an even index the elements on both sides
+  const int ney = (iy & 1) ? 1 : 2, nex = (ix & 1) ? 1 : 2;
+  const int ey0 = (iy & 1) ? (iy - 1) / 2 : iy / 2 - 1;
+  const int ex0 = (ix & 1) ? (ix - 1) / 2 : ix / 2 - 1;
+  const int b0 = (iy & 1) ? 1 : 2, c0 = (ix & 1) ? 1 : 2;
+  const TF *fe = static_cast<const TF *>(d.fe) + (size_t)18 * D.elem_off;
+  const size_t ne = (size_t)D.ne;
+  double Fx = 0.0, Fy = 0.0;
+  for (int t = 0; t < ney; ++t) {
+    const int ey = ey0 + t, bb = b0 - 2 * t;
+    for (int s = 0; s < nex; ++s) {
+      const int ex = ex0 + s, c = c0 - 2 * s;
+      const size_t e = (size_t)ey * D.nx + ex;
+      const int a = 3 * bb + c;
+      Fx += (double)fe[a * ne + e];
+      Fy += (double)fe[(9 + a) * ne + e];
+    }
+  }
+  double vx, vy;
+  velocity_update(p, d.nc + (size_t)6 * D.node_off, (size_t)D.nn, j, vin[j], vin[D.nn + j], Fx,
+                  Fy, vx, vy);
+  vout[j] = vx;
+  vout[D.nn + j] = vy;
+}
+
+// ---------------------------------------------------------------------------
+// Fused subcycle on one tile of EX x EY elements. The tile's first column
+// and row are a halo (the elements left of and below the owned
+// (EX-1) x (EY-1) block): their forces are recomputed here (their stress is
+// not stored; its owner stores it), so every node the tile owns -- CG2
+// columns [2 x0, 2 x0 + 2 (EX-1)) and rows likewise, plus the last column /
+// row of the domain for the last tile -- finds the forces of all its elements
+// in LDS. The forces never leave the chip. v and S are read from the *_in
+// buffers and written to the *_out buffers (double buffering: neighbouring
+// tiles read the old values while this one writes the new).
+// ---------------------------------------------------------------------------
+template <int NS, int NA, class T, class TS, bool AFF, int EX, int EY>
+__device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p, const Tile t,
+                                           const Bufs &b, T (*fl)[EX * EY]) {
+  constexpr int TX = EX - 1, TY = EY - 1, NT = EX * EY;
+  const DomDev D = d.doms[t.dom];
+  const DomBufs<TS> B(b, D, NS);
+  const int tid = (int)threadIdx.x;
+  {
+    const int lx = tid % EX, ly = tid / EX;
+    const int ex = t.x0 - 1 + lx, ey = t.y0 - 1 + ly;
+    if (ex >= 0 && ey >= 0 && ex < D.nx && ey < D.ny) {
+      const int el = ey * D.nx + ex;
+      T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
+      element_update<NS, NA, T, TS, AFF>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx,
+                                         fy);
+      if (lx > 0 && ly > 0) store_stress<NS, T, TS>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        fl[a][tid] = fx[a];
+        fl[9 + a][tid] = fy[a];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- nodes owned by the tile, row-major (consecutive lanes, consecutive
+  // nodes); each lane takes up to R of them and issues all their loads before
+  // the first update ----
+  const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
+  const size_t nn = (size_t)D.nn;
+  const double *nc = d.nc + (size_t)6 * D.node_off;
+  const int ix0 = 2 * t.x0, iy0 = 2 * t.y0;
+  const int ix1 = (t.x0 + TX >= D.nx) ? NX : ix0 + 2 * TX;
+  const int iy1 = (t.y0 + TY >= D.ny) ? NY : iy0 + 2 * TY;
+  const int w = ix1 - ix0, n = w * (iy1 - iy0);
+  constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;
+  int jn[R], ixs[R], iys[R];
+  bool act[R], bnd[R];
+  double ux[R], uy[R], o[R][6];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int k = tid + m * NT;
+    act[m] = k < n;
+    ixs[m] = ix0 + (act[m] ? k % w : 0);
+    iys[m] = iy0 + (act[m] ? k / w : 0);
+    jn[m] = iys[m] * NX + ixs[m];
+    bnd[m] = ixs[m] == 0 || iys[m] == 0 || ixs[m] == NX - 1 || iys[m] == NY - 1;
+    if (act[m] && !bnd[m]) {
+      ux[m] = B.v_in[jn[m]];
+      uy[m] = B.v_in[nn + jn[m]];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[m][c] = nc[c * nn + jn[m]];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    if (!act[m]) continue;
+    if (bnd[m]) {
+      B.v_out[jn[m]] = 0.0;
+      B.v_out[nn + jn[m]] = 0.0;
+      continue;
+    }
+    const int ix = ixs[m], iy = iys[m];
+    const int ney = (iy & 1) ? 1 : 2, nex = (ix & 1) ? 1 : 2;
+    const int ey0 = (iy & 1) ? (iy - 1) / 2 : iy / 2 - 1;
+    const int ex0 = (ix & 1) ? (ix - 1) / 2 : ix / 2 - 1;
+    const int b0 = (iy & 1) ? 1 : 2, c0 = (ix & 1) ? 1 : 2;
+    double Fx = 0.0, Fy = 0.0;
+    for (int tt = 0; tt < ney; ++tt) {
+      const int ly = ey0 + tt - t.y0 + 1, bb = b0 - 2 * tt;
+      for (int ss = 0; ss < nex; ++ss) {
+        const int lx = ex0 + ss - t.x0 + 1, c = c0 - 2 * ss;
+        const int a = 3 * bb + c, le = ly * EX + lx;
+        Fx += (double)fl[a][le];
+        Fy += (double)fl[9 + a][le];
+      }
+    }
+    double vx, vy;
+    velocity_update6(p, o[m], ux[m], uy[m], Fx, Fy, vx, vy);
+    B.v_out[jn[m]] = vx;
+    B.v_out[nn + jn[m]] = vy;
+  }
+}
+
+// Fused subcycle kernel. persist == 0: an ordinary launch, one tile per
+// workgroup, one subcycle (buffers b0). persist != 0: a cooperative launch
+// whose workgroups stay resident for n_sub subcycles; in subcycle i every
+// workgroup takes the tiles blockIdx.x, blockIdx.x + gridDim.x, ... (the grid
+// is a multiple of 8, so a workgroup stays on one XCD's band of the XCD-ordered
+// tile table), with buffers b0 for even i and b1 (= b0 swapped) for odd i,
+// and a grid-wide barrier between subcycles. Every workgroup runs the same
+// number of barriers, so the grid always drains.
+template <int NS, int NA, class T, class TS, bool AFF, int EX, int EY>
+__global__ void __launch_bounds__(EX *EY) k_fused(DevArrays d, KParams p, const Tile *tiles,
+                                                   int ntiles, Bufs b0, Bufs b1, int n_sub,
+                                                   int persist) {
+  __shared__ T fl[18][EX * EY];
+  if (!persist) {
+    fused_tile<NS, NA, T, TS, AFF, EX, EY>(d, p, tiles[blockIdx.x], b0, fl);
+    return;
+  }
+  cooperative_groups::grid_group g = cooperative_groups::this_grid();
+  for (int it = 0; it < n_sub; ++it) {
+    const Bufs &b = (it & 1) ? b1 : b0;
+    for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
+      fused_tile<NS, NA, T, TS, AFF, EX, EY>(d, p, tiles[i], b, fl);
+      __syncthreads();  // the next tile reuses the LDS
+    }
+    if (it + 1 < n_sub) g.sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Start of a time step: lumped masses gathered per node in ascending element
+// order from per-element integrals computed on the fly, air stress, and the
+// six node constants of the velocity update: c = M^H/dt, m^A rho_o C_o,
+// g = c v^n + m^A tau_a (2), ocean velocity (2).
+// ---------------------------------------------------------------------------
+template <int NS, int NA>
+__global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams p,
+                                                           const double *v) {
+  using Q = Quad<Ngp<NS>::value>;
+  const Blk blk = d.nblk[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int j = blk.first + (int)threadIdx.x;
+  if (j >= D.nn) return;
+  const int NX = 2 * D.nx + 1;
+  const int ix = j % NX, iy = j / NX;
+  const size_t o = 2 * (size_t)D.node_off;
+
+  double MH = 0.0, mA = 0.0;
+  const size_t ne = (size_t)D.ne;
+  const double *Hd = d.H + (size_t)NA * D.elem_off;
+  const double *Ad = d.A + (size_t)NA * D.elem_off;
+  for (int t = 0; t < 2; ++t) {
+    // candidate element rows: iy odd -> (iy-1)/2 only; iy even -> iy/2-1 and iy/2
+    const int ey = (iy & 1) ? ((t == 0) ? (iy - 1) / 2 : -1) : iy / 2 - 1 + t;
+    if (ey < 0 || ey >= D.ny) continue;
+    const int b = iy - 2 * ey;
+    for (int s = 0; s < 2; ++s) {
+      const int ex = (ix & 1) ? ((s == 0) ? (ix - 1) / 2 : -1) : ix / 2 - 1 + s;
+      if (ex < 0 || ex >= D.nx) continue;
+      const int cc = ix - 2 * ex;
+      const int a = 3 * b + cc;
+      const size_t e = (size_t)ey * D.nx + ex;
+      const Cell<double> cell = load_cell<double>(D, d.vert, ex, ey);
+      double Hc[NA], Ac[NA];
+#pragma unroll
+      for (int k = 0; k < NA; ++k) {
+        Hc[k] = Hd[k * ne + e];
+        Ac[k] = Ad[k * ne + e];
+      }
+      double sh = 0.0, sa = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q::NG; ++q) {
+        double J00, J01, J10, J11;
+        cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+        const double wd = Q::w(q) * (J00 * J11 - J01 * J10);
+        double hs = 0.0, as = 0.0;
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          hs += Hc[k] * Q::psi(k, q);
+          as += Ac[k] * Q::psi(k, q);
+        }
+        const double h = fmax(0.0, hs), ac = fmin(1.0, fmax(0.0, as));
+        double phi = 0.0;
+        switch (a) {  // keep the table lookup a constant per branch
+#define MEVP_PHI_CASE(A_) case A_: phi = Q::phi(A_, q); break;
+          MEVP_PHI_CASE(0) MEVP_PHI_CASE(1) MEVP_PHI_CASE(2) MEVP_PHI_CASE(3) MEVP_PHI_CASE(4)
+          MEVP_PHI_CASE(5) MEVP_PHI_CASE(6) MEVP_PHI_CASE(7) MEVP_PHI_CASE(8)
+#undef MEVP_PHI_CASE
+        }
+        sh += wd * p.rho_i * h * phi;
+        sa += wd * ac * phi;
+      }
+      MH += sh;
+      mA += sa;
+    }
+  }
+  const double wx = d.wind[o + j], wy = d.wind[o + D.nn + j];
+  const double sp = sqrt(wx * wx + wy * wy);
+  const double c = MH * p.inv_dt;
+  double *nc = d.nc + (size_t)6 * D.node_off;
+  const size_t nn = (size_t)D.nn;
+  nc[j] = c;
+  nc[nn + j] = mA * p.rhoCo;
+  nc[2 * nn + j] = c * v[o + j] + mA * (p.rhoCa * sp * wx);
+  nc[3 * nn + j] = c * v[o + D.nn + j] + mA * (p.rhoCa * sp * wy);
+  nc[4 * nn + j] = d.ocean[o + j];
+  nc[5 * nn + j] = d.ocean[o + D.nn + j];
+}
+
+// Per domain: 1 if every cell is a parallelogram (its edge vectors agree
+// exactly in double), 0 otherwise. The flag starts at 1; any lane that finds
+// a general cell stores 0.
+__global__ void __launch_bounds__(kElemBlock) k_cell_shape(DevArrays d, int dom, int *flag) {
+  const DomDev D = d.doms[dom];
+  for (int el = blockIdx.x * blockDim.x + threadIdx.x; el < D.ne; el += gridDim.x * blockDim.x) {
+    const int ex = el % D.nx, ey = el / D.nx;
+    const double *VX = d.vert + 2 * (size_t)D.vert_off;
+    const double *VY = VX + D.nv;
+    const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
+    const bool par = (VX[i0 + 1] - VX[i0] == VX[i2 + 1] - VX[i2]) &&
+                     (VY[i0 + 1] - VY[i0] == VY[i2 + 1] - VY[i2]) &&
+                     (VX[i2] - VX[i0] == VX[i2 + 1] - VX[i0 + 1]) &&
+                     (VY[i2] - VY[i0] == VY[i2 + 1] - VY[i0 + 1]);
+    if (!par) *flag = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Advection of H and A (Sec. 2, Eq. (si:ad); DG with the upwind flux):
+// one stage of the three-stage SSP Runge-Kutta scheme,
+//   U_out = a U^n + b (U_in + dt M^-1 R(U_in)),
+//   R_k = int_K U v.grad psi_k - sum_edges int_edge (v.n) U_up psi_k,
+// U_up the trace of K where v.n >= 0 and of the neighbour otherwise (of K on
+// the domain boundary), v the CG2 velocity held fixed, 3x3 Gauss points in the
+// cell and 3 per edge. One element per lane, both fields, bilinear cells.
+// ---------------------------------------------------------------------------
+constexpr double kAdvW[3] = {5.0 / 18.0, 4.0 / 9.0, 5.0 / 18.0};
+constexpr double kAdvX[3] = {0.11270166537925831148207346002176, 0.5,
+                             0.88729833462074168851792653997824};
+
+// gradient of DG function k in reference coordinates
+__device__ __forceinline__ void dg_grad_ref(int k, double xi, double eta, double &gx, double &ge) {
+  const double s = xi - 0.5, t = eta - 0.5;
+  gx = (k == 1) ? 1.0 : (k == 3) ? 2.0 * s : (k == 4) ? t : 0.0;
+  ge = (k == 2) ? 1.0 : (k == 5) ? 2.0 * t : (k == 4) ? s : 0.0;
+}
+
+template <int NA>
+__device__ __forceinline__ double dg_eval(const double (&c)[NA], double xi, double eta) {
+  double u = 0.0;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) u += c[k] * dg_fn(k, xi, eta);
+  return u;
+}
+
+__device__ __forceinline__ void cg2_eval(const double (&vx)[9], const double (&vy)[9], double xi,
+                                         double eta, double &ux, double &uy) {
+  ux = 0.0;
+  uy = 0.0;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const double ph = q2_1d(a % 3, xi) * q2_1d(a / 3, eta);
+    ux += vx[a] * ph;
+    uy += vy[a] * ph;
+  }
+}
+
+template <int NA>
+__global__ void __launch_bounds__(kElemBlock) k_advect(DevArrays d, const Blk *blks,
+                                                       const double *v, const double *Hn,
+                                                       const double *An, const double *Hin,
+                                                       const double *Ain, double *Hout,
+                                                       double *Aout, double dt, double ca,
+                                                       double cb) {
+  const Blk blk = blks[blockIdx.x];
+  const DomDev D = d.doms[blk.dom];
+  const int el = blk.first + (int)threadIdx.x;
+  if (el >= D.ne) return;
+  const int ex = el % D.nx, ey = el / D.nx;
+  const size_t ne = (size_t)D.ne, off = (size_t)NA * D.elem_off;
+  const Cell<double> cell = load_cell<double>(D, d.vert, ex, ey);
+  double vx[9], vy[9];
+  load_velocity<double>(D, v, ex, ey, vx, vy);
+  double Ue[2][NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    Ue[0][k] = Hin[off + k * ne + el];
+    Ue[1][k] = Ain[off + k * ne + el];
+  }
+  double R[2][NA], M[NA][NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    R[0][k] = R[1][k] = 0.0;
+#pragma unroll
+    for (int l = 0; l < NA; ++l) M[k][l] = 0.0;
+  }
+  // ---- cell integral and mass matrix ----
+#pragma unroll
+  for (int qy = 0; qy < 3; ++qy)
+#pragma unroll
+    for (int qx = 0; qx < 3; ++qx) {
+      const double xi = kAdvX[qx], eta = kAdvX[qy], w = kAdvW[qx] * kAdvW[qy];
+      double J00, J01, J10, J11;
+      cell.jac(xi, eta, J00, J01, J10, J11);
+      const double det = J00 * J11 - J01 * J10;
+      double ux, uy;
+      cg2_eval(vx, vy, xi, eta, ux, uy);
+      // w |J| v.grad psi_k = w v . adj(J)^T grad_ref psi_k
+      const double uh = dg_eval<NA>(Ue[0], xi, eta), ua = dg_eval<NA>(Ue[1], xi, eta);
+#pragma unroll
+      for (int k = 0; k < NA; ++k) {
+        double gx, ge;
+        dg_grad_ref(k, xi, eta, gx, ge);
+        const double vg = w * (ux * (J11 * gx - J10 * ge) + uy * (J00 * ge - J01 * gx));
+        R[0][k] += uh * vg;
+        R[1][k] += ua * vg;
+#pragma unroll
+        for (int l = 0; l < NA; ++l) M[k][l] += w * det * dg_fn(k, xi, eta) * dg_fn(l, xi, eta);
+      }
+    }
+  // ---- edge fluxes: bottom, right, top, left, counter-clockwise ----
+  const double *VX = d.vert + 2 * (size_t)D.vert_off;
+  const double *VY = VX + D.nv;
+  const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
+  const int vid[4] = {i0, i0 + 1, i2, i2 + 1};
+  const int from[4] = {0, 1, 3, 2}, to[4] = {1, 3, 2, 0};
+  const int ddx[4] = {0, 1, 0, -1}, ddy[4] = {-1, 0, 1, 0};
+#pragma unroll
+  for (int ed = 0; ed < 4; ++ed) {
+    const double tx = VX[vid[to[ed]]] - VX[vid[from[ed]]];
+    const double ty = VY[vid[to[ed]]] - VY[vid[from[ed]]];
+    const double nlx = ty, nly = -tx;  // outward normal times edge length
+    const int fx = ex + ddx[ed], fy = ey + ddy[ed];
+    const bool nb = fx >= 0 && fy >= 0 && fx < D.nx && fy < D.ny;
+    double Un[2][NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const size_t f = nb ? (size_t)fy * D.nx + fx : (size_t)el;
+      Un[0][k] = Hin[off + k * ne + f];
+      Un[1][k] = Ain[off + k * ne + f];
+    }
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      const double u = kAdvX[g];
+      const double xi = ed == 0 ? u : ed == 1 ? 1.0 : ed == 2 ? 1.0 - u : 0.0;
+      const double eta = ed == 0 ? 0.0 : ed == 1 ? u : ed == 2 ? 1.0 : 1.0 - u;
+      double ux, uy;
+      cg2_eval(vx, vy, xi, eta, ux, uy);
+      const double vn = ux * nlx + uy * nly;
+      double uh, ua;
+      if (vn >= 0.0 || !nb) {
+        uh = dg_eval<NA>(Ue[0], xi, eta);
+        ua = dg_eval<NA>(Ue[1], xi, eta);
+      } else {  // the same point in the neighbour's reference coordinates
+        const double xn = ed == 0 ? u : ed == 1 ? 0.0 : ed == 2 ? 1.0 - u : 1.0;
+        const double en = ed == 0 ? 1.0 : ed == 1 ? u : ed == 2 ? 0.0 : 1.0 - u;
+        uh = dg_eval<NA>(Un[0], xn, en);
+        ua = dg_eval<NA>(Un[1], xn, en);
+      }
+#pragma unroll
+      for (int k = 0; k < NA; ++k) {
+        const double wp = kAdvW[g] * vn * dg_fn(k, xi, eta);
+        R[0][k] -= wp * uh;
+        R[1][k] -= wp * ua;
+      }
+    }
+  }
+  // ---- M^-1 R (Cholesky-free LDL^T of the small SPD matrix) and the stage ----
+  double L[NA][NA], dv[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    double dj = M[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k] * dv[k];
+    dv[j] = dj;
+#pragma unroll
+    for (int i = j + 1; i < NA; ++i) {
+      double sum = M[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) sum -= L[i][k] * L[j][k] * dv[k];
+      L[i][j] = sum / dj;
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    double x[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      x[i] = R[f][i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) x[i] -= L[i][k] * x[k];
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) x[i] /= dv[i];
+#pragma unroll
+    for (int i = NA - 1; i >= 0; --i)
+#pragma unroll
+      for (int k = i + 1; k < NA; ++k) x[i] -= L[k][i] * x[k];
+    const double *Un0 = f == 0 ? Hn : An;
+    double *Uo = f == 0 ? Hout : Aout;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const size_t i = off + k * ne + el;
+      Uo[i] = ca * Un0[i] + cb * (Ue[f][k] + dt * x[k]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+template <int NS, int NA>
+inline hipError_t begin_step_t(const DevArrays &d, const KParams &p, const double *v, int n_nblk,
+                               hipStream_t s) {
+  hipLaunchKernelGGL((k_begin_step<NS, NA>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p, v);
+  return hipGetLastError();
+}
+
+// Two-phase subcycle: element kernel(s) (parallelogram blocks, general
+// blocks), then the node kernel.
+template <int NS, int NA, class T>
+inline hipError_t two_phase_t(const DevArrays &d, const KParams &p, const Launch &L, Bufs b,
+                              hipStream_t s) {
+  if (L.n_aff > 0)
+    hipLaunchKernelGGL((k_element<NS, NA, T, T, true>), dim3(L.n_aff), dim3(kElemBlock), 0, s, d, p,
+                       d.eblk, b);
+  if (L.n_gen > 0)
+    hipLaunchKernelGGL((k_element<NS, NA, T, T, false>), dim3(L.n_gen), dim3(kElemBlock), 0, s, d, p,
+                       d.eblk + L.n_aff, b);
+  return hipGetLastError();
+}
+
+// Fused subcycle(s): tile kernel(s), parallelogram tiles first.
+template <int NS, int NA, class T, bool AFF, int EX, int EY>
+inline hipError_t fused_one(const DevArrays &d, const KParams &p, const Tile *tiles, int ntiles,
+                            const FusedArgs &f, hipStream_t s) {
+  auto kern = k_fused<NS, NA, T, T, AFF, EX, EY>;
+  if (!f.persist) {
+    hipLaunchKernelGGL(kern, dim3(ntiles), dim3(EX * EY), 0, s, d, p, tiles, ntiles, f.b0, f.b1, 1, 0);
+    return hipGetLastError();
+  }
+  int per_cu = 0, dev = 0, n_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, EX * EY, 0);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  int grid = per_cu * n_cu;
+  if (grid > ntiles) grid = ntiles;
+  if (grid >= kNumXcd) grid -= grid % kNumXcd;
+  if (grid < 1) return hipErrorInvalidValue;
+  DevArrays dd = d;
+  KParams pp = p;
+  const Tile *tt = tiles;
+  int nt = ntiles, ns = f.n_sub, one = 1;
+  Bufs b0 = f.b0, b1 = f.b1;
+  void *args[] = {&dd, &pp, &tt, &nt, &b0, &b1, &ns, &one};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid), dim3(EX * EY),
+                                    args, 0, s);
+}
+
+template <int NS, int NA, class T, int EX, int EY>
+inline hipError_t fused_shape(const DevArrays &d, const KParams &p, const Launch &L,
+                              const FusedArgs &f, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (L.n_aff > 0) e = fused_one<NS, NA, T, true, EX, EY>(d, p, d.tiles, L.n_aff, f, s);
+  if (e == hipSuccess && L.n_gen > 0)
+    e = fused_one<NS, NA, T, false, EX, EY>(d, p, d.tiles + L.n_aff, L.n_gen, f, s);
+  return e;
+}
+
+template <int NS, int NA, class T>
+inline hipError_t fused_t(const DevArrays &d, const KParams &p, const Launch &L,
+                          const FusedArgs &f, hipStream_t s) {
+  if (f.shape == 0) return fused_shape<NS, NA, T, kTileShapes[0][0], kTileShapes[0][1]>(d, p, L, f, s);
+  if constexpr (NA == 1) {  // the other tile shapes are built for one ice dof only
+    if (f.shape == 1) return fused_shape<NS, NA, T, kTileShapes[1][0], kTileShapes[1][1]>(d, p, L, f, s);
+    if (f.shape == 2) return fused_shape<NS, NA, T, kTileShapes[2][0], kTileShapes[2][1]>(d, p, L, f, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+
+// Launchers of one n_s for every n_a and precision; each kernel translation
+// unit instantiates them for its n_s.
+template <int NS>
+inline hipError_t begin_step_ns(const DevArrays &d, const KParams &p, int n_a, const double *v,
+                                int n_nblk, hipStream_t s) {
+  if (n_a == 1) return begin_step_t<NS, 1>(d, p, v, n_nblk, s);
+  if (n_a == 3) return begin_step_t<NS, 3>(d, p, v, n_nblk, s);
+  if (n_a == 6) return begin_step_t<NS, 6>(d, p, v, n_nblk, s);
+  return hipErrorInvalidValue;
+}
+
+template <int NS>
+inline hipError_t two_phase_ns(const DevArrays &d, const KParams &p, int n_a, bool mixed,
+                               const Launch &L, Bufs b, hipStream_t s) {
+#define MEVP_TP(NA_) \
+  if (n_a == NA_) return mixed ? two_phase_t<NS, NA_, float>(d, p, L, b, s) : two_phase_t<NS, NA_, double>(d, p, L, b, s);
+  MEVP_TP(1) MEVP_TP(3) MEVP_TP(6)
+#undef MEVP_TP
+  return hipErrorInvalidValue;
+}
+
+template <int NS>
+inline hipError_t fused_ns(const DevArrays &d, const KParams &p, int n_a, bool mixed,
+                           const Launch &L, const FusedArgs &f, hipStream_t s) {
+#define MEVP_FU(NA_) \
+  if (n_a == NA_) return mixed ? fused_t<NS, NA_, float>(d, p, L, f, s) : fused_t<NS, NA_, double>(d, p, L, f, s);
+  MEVP_FU(1) MEVP_FU(3) MEVP_FU(6)
+#undef MEVP_FU
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+}  // namespace mevp

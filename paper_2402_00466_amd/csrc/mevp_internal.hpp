@@ -40,6 +40,14 @@ struct Bufs {
   void *S_out;
 };
 
+// Launch arguments of the fused subcycle kernel.
+struct FusedArgs {
+  Bufs b0, b1;     // buffers of even / odd subcycles (b1 = b0 swapped)
+  int shape;       // index into kTileShapes
+  int persist;     // 1: one cooperative launch for n_sub subcycles
+  int n_sub;
+};
+
 // Leading blocks (or tiles) of parallelogram-cell domains, then the rest.
 struct Launch {
   int n_aff, n_gen;
@@ -62,6 +70,7 @@ struct DevArrays {
   const double *vert;  // [dom][2][nv]
   const double *H;     // [dom][n_a][ne]
   const double *A;
+  double *adv;         // advection stages: [4][dom][n_a][ne] (H1, A1, H2, A2)
   const double *wind;  // [dom][2][nn]
   const double *ocean;
   double *v;           // [dom][2][nn] (two buffers: v and v + 2 * total nodes)
@@ -73,11 +82,12 @@ struct DevArrays {
 
 constexpr int kElemBlock = 256;
 constexpr int kNodeBlock = 256;
-// fused kernel: a 17 x 15 element tile per workgroup, 16 x 14 of them owned
-// (16 owned elements = one 128-byte line of a double array per row)
-constexpr int kTileEX = 17;
-constexpr int kTileEY = 15;
-constexpr int kTileThreads = kTileEX * kTileEY;
+// fused kernel tile shapes (elements per workgroup including the one-element
+// halo; the owned block is one smaller in each direction): 17 x 15 (16 x 14
+// owned, 16 owned elements = one 128-byte line of a double array per row),
+// 17 x 17 and 33 x 15
+constexpr int kNumTileShapes = 3;
+constexpr int kTileShapes[kNumTileShapes][2] = {{17, 15}, {17, 17}, {33, 15}};
 // workgroups are dealt to the 8 XCDs of the chip in turn
 constexpr int kNumXcd = 8;
 
@@ -89,9 +99,23 @@ hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, i
 hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, int n_nblk, Bufs b,
                              hipStream_t s);
 hipError_t launch_fused_subcycle(const DevArrays &d, const KParams &p, int n_s, int n_a,
-                                 bool mixed, const Launch &L, Bufs b, hipStream_t s);
+                                 bool mixed, const Launch &L, const FusedArgs &f, hipStream_t s);
 hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s);
+hipError_t launch_advect_stage(const DevArrays &d, int n_a, int n_eblk, const double *v,
+                               const double *Hn, const double *An, const double *Hin,
+                               const double *Ain, double *Hout, double *Aout, double dt, double ca,
+                               double cb, hipStream_t s);
 hipError_t launch_fill(void *dst, size_t n_words32, uint32_t value, hipStream_t s);
+// per-n_s launchers (mevp_kernels_ns{3,6,8}.hip)
+hipError_t begin_step_ns3(const DevArrays &, const KParams &, int, const double *, int, hipStream_t);
+hipError_t begin_step_ns6(const DevArrays &, const KParams &, int, const double *, int, hipStream_t);
+hipError_t begin_step_ns8(const DevArrays &, const KParams &, int, const double *, int, hipStream_t);
+hipError_t two_phase_ns3(const DevArrays &, const KParams &, int, bool, const Launch &, Bufs, hipStream_t);
+hipError_t two_phase_ns6(const DevArrays &, const KParams &, int, bool, const Launch &, Bufs, hipStream_t);
+hipError_t two_phase_ns8(const DevArrays &, const KParams &, int, bool, const Launch &, Bufs, hipStream_t);
+hipError_t fused_ns3(const DevArrays &, const KParams &, int, bool, const Launch &, const FusedArgs &, hipStream_t);
+hipError_t fused_ns6(const DevArrays &, const KParams &, int, bool, const Launch &, const FusedArgs &, hipStream_t);
+hipError_t fused_ns8(const DevArrays &, const KParams &, int, bool, const Launch &, const FusedArgs &, hipStream_t);
 hipError_t launch_convert_d2f(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_convert_f2d(const float *src, double *dst, size_t n, hipStream_t s);
 hipError_t launch_check_finite(const double *p, size_t n, int *flag, int bit, hipStream_t s);

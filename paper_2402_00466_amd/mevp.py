@@ -17,11 +17,13 @@ from . import build as _build
 
 FP64 = 0
 MIXED = 1
-STRATEGIES = {"fused": 0, "two_phase": 1}
+STRATEGIES = {"fused": 0, "two_phase": 1, "persistent": 2}
+STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
+TILES = [(16, 14), (16, 16), (32, 14)]
 _PREC = {"fp64": FP64, "f64": FP64, "mixed": MIXED}
 
 STATUS = {0: "MEVP_OK", -1: "MEVP_EINVAL", -2: "MEVP_ENOMEM", -3: "MEVP_EDEVICE",
-          -4: "MEVP_ESTATE", -5: "MEVP_ENONFINITE", -6: "MEVP_EUNSUPPORTED"}
+          -4: "MEVP_ESTATE", -5: "MEVP_ENONFINITE", -6: "MEVP_EUNSUPPORTED", -7: "MEVP_EINTERNAL"}
 
 
 class MevpError(RuntimeError):
@@ -38,6 +40,10 @@ class CParams(C.Structure):
                [("relax_form", C.c_int)]
 
 
+class CConfig(C.Structure):
+    _fields_ = [("strategy", C.c_int), ("tile_nx", C.c_int), ("tile_ny", C.c_int)]
+
+
 class CDomain(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("n_s", C.c_int), ("n_a", C.c_int)]
 
@@ -45,6 +51,8 @@ class CDomain(C.Structure):
 _lib = None
 
 EXPORTS = ["mevp_default_params", "mevp_workspace_size", "mevp_create", "mevp_set_strategy",
+           "mevp_set_config", "mevp_get_config", "mevp_set_graph", "mevp_tune",
+           "mevp_advect", "mevp_get_fields",
            "mevp_set_params",
            "mevp_set_geometry", "mevp_set_fields", "mevp_set_forcing", "mevp_set_state",
            "mevp_step", "mevp_begin_step", "mevp_subcycles", "mevp_get_state", "mevp_sync",
@@ -73,6 +81,12 @@ def lib():
                               C.POINTER(vp)]
     L.mevp_set_params.argtypes = [vp, C.POINTER(CParams)]
     L.mevp_set_strategy.argtypes = [vp, i]
+    L.mevp_set_config.argtypes = [vp, C.POINTER(CConfig)]
+    L.mevp_set_graph.argtypes = [vp, i]
+    L.mevp_tune.argtypes = [vp, i, C.c_char_p, C.POINTER(CConfig)]
+    L.mevp_advect.argtypes = [vp]
+    L.mevp_get_fields.argtypes = [vp, i, dp, dp]
+    L.mevp_get_config.argtypes = [vp, C.POINTER(CConfig)]
     L.mevp_set_geometry.argtypes = [vp, i, dp]
     L.mevp_set_fields.argtypes = [vp, i, dp, dp]
     L.mevp_set_forcing.argtypes = [vp, i, dp, dp]
@@ -222,6 +236,27 @@ class Context:
         _check("mevp_set_strategy", lib().mevp_set_strategy(self._h, STRATEGIES[strategy]))
         self.strategy = strategy
 
+    def set_config(self, strategy: str, tile=(16, 14)):
+        cfg = CConfig(STRATEGIES[strategy], int(tile[0]), int(tile[1]))
+        _check("mevp_set_config", lib().mevp_set_config(self._h, C.byref(cfg)))
+        self.strategy = strategy
+
+    def set_graph(self, enable: bool):
+        _check("mevp_set_graph", lib().mevp_set_graph(self._h, int(bool(enable))))
+
+    def tune(self, n_trial: int = 20, cache_path: str | None = None):
+        """Autotune the launch configuration (see mevp_tune); returns (strategy, tile)."""
+        cfg = CConfig()
+        path = cache_path.encode() if cache_path else None
+        _check("mevp_tune", lib().mevp_tune(self._h, int(n_trial), path, C.byref(cfg)))
+        self.strategy = STRATEGY_NAMES[cfg.strategy]
+        return STRATEGY_NAMES[cfg.strategy], (cfg.tile_nx, cfg.tile_ny)
+
+    def get_config(self):
+        cfg = CConfig()
+        _check("mevp_get_config", lib().mevp_get_config(self._h, C.byref(cfg)))
+        return STRATEGY_NAMES[cfg.strategy], (cfg.tile_nx, cfg.tile_ny)
+
     def set_params(self, params: Params):
         _check("mevp_set_params", lib().mevp_set_params(self._h, C.byref(params.to_c())))
         self.params = params
@@ -256,7 +291,20 @@ class Context:
     def subcycles(self, n: int):
         _check("mevp_subcycles", lib().mevp_subcycles(self._h, int(n)))
 
+    def advect(self):
+        """Advect H and A of every domain over one step (mevp_advect)."""
+        _check("mevp_advect", lib().mevp_advect(self._h))
+
     # -- copy-out -------------------------------------------------------
+    def get_fields(self, dom):
+        torch = self._torch
+        d = self._dom(dom)
+        H = torch.empty((d.n_a, d.ne), dtype=torch.float64, device=self.device)
+        A = torch.empty((d.n_a, d.ne), dtype=torch.float64, device=self.device)
+        _check("mevp_get_fields", lib().mevp_get_fields(
+            self._h, dom, C.c_void_p(H.data_ptr()), C.c_void_p(A.data_ptr())))
+        return H, A
+
     def get_state(self, dom):
         torch = self._torch
         d = self._dom(dom)

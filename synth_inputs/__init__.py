@@ -42,7 +42,9 @@ __all__ = [
 
 #: seeds of the named workloads; the batched one derives per-domain seeds from 466
 WORKLOAD_SEEDS = {"32x32-dg1": 1001, "256x256-dg2": 1002, "1024x1024-dg2": 1003,
-                  "2048x2048-dg2": 1005, "batch64-dg2": 466}
+                  "2048x2048-dg2": 1005, "batch64-dg2": 466,
+                  "1024x1024-ns8": 1008, "1024x1024-dg2-bilinear": 1009,
+                  "2048x2048-dg2-bilinear": 1010}
 
 #: wind gyre peak speed [m/s], angular rotation rate [1/s], ocean peak [m/s]
 WIND_PEAK = 10.0
@@ -191,6 +193,9 @@ def named_workload(name: str) -> list[DomainInputs]:
       1024x1024-dg2   1024 x 1024 cells on 512 km (0.5 km)
       2048x2048-dg2   2048 x 2048 cells on 512 km (0.25 km)
       batch64-dg2     64 square domains of 512 km, sides 64..512 cells (seeded)
+      1024x1024-ns8   1024 x 1024 on 512 km, 8 stress dofs (the Q2-gradient space)
+      *-bilinear      the same meshes with interior vertices moved by <= 0.15 h,
+                      so every cell is a general quadrilateral
     """
     seed = WORKLOAD_SEEDS[name]
     if name == "32x32-dg1":
@@ -200,6 +205,10 @@ def named_workload(name: str) -> list[DomainInputs]:
         return [make_domain(n, n, 6, 1, 1000 * seed + d, wind_phase=phases[d])
                 for d, n in enumerate(sizes)]
     n = int(name.split("x")[0])
+    if name.endswith("-ns8"):
+        return [make_domain(n, n, 8, 1, seed)]
+    if name.endswith("-bilinear"):
+        return [make_domain(n, n, 6, 1, seed, perturb=0.15)]
     return [make_domain(n, n, 6, 1, seed)]
 
 

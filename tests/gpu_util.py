@@ -28,12 +28,14 @@ def field_errors(v, S, vr, Sr):
 
 
 def gpu_run(domains, n_steps, n_sub, precision="fp64", states=None, params=None,
-            subcycles_only=False, strategy="fused"):
+            subcycles_only=False, strategy="fused", tile=None):
     """Run every domain in ONE context; return [(v, S)] as numpy arrays."""
     import torch
     import paper_2402_00466_amd as M
     ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in domains], params=params,
                     precision=precision, strategy=strategy)
+    if tile is not None:
+        ctx.set_config(strategy, tile)
     for k, d in enumerate(domains):
         ctx.upload(k, d)
         if states is not None:

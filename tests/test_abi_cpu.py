@@ -97,6 +97,7 @@ def _create(M, params=None, ws=0x10000000, ws_bytes=None, doms=((8, 8, 6, 1),), 
 
 
 @pytest.mark.parametrize("field,value", [("alpha", 0.0), ("dt", -1.0), ("DeltaMin", 0.0),
+                                         ("DeltaMin", 1e-200),
                                          ("beta", -1.0), ("Pstar", float("nan")),
                                          ("C", float("inf")), ("rho_i", 0.0), ("relax_form", 2)])
 def test_create_rejects_bad_params_before_device(M, field, value):

@@ -55,7 +55,7 @@ WHOLE_RUNS = [
 ]
 
 
-@pytest.mark.parametrize("strategy", ["fused", "two_phase"])
+@pytest.mark.parametrize("strategy", ["fused", "two_phase", "persistent"])
 @pytest.mark.parametrize("case", WHOLE_RUNS, ids=lambda c: "x".join(map(str, c[:4])))
 def test_whole_run_fp64(case, strategy):
     nx, ny, ns, na, h, pert, ho, steps, nsub = case
@@ -97,12 +97,16 @@ def _few_subcycles(name, n_sub, precision, tol, dom_index=0):
     _assert_close(field_errors(v, S, vr, Sr), tol, f"{name} {precision} {n_sub} subcycles")
 
 
-@pytest.mark.parametrize("name", ["256x256-dg2", "1024x1024-dg2", "2048x2048-dg2"])
+FULL_SIZE = ["256x256-dg2", "1024x1024-dg2", "2048x2048-dg2", "1024x1024-ns8",
+             "1024x1024-dg2-bilinear", "2048x2048-dg2-bilinear"]
+
+
+@pytest.mark.parametrize("name", FULL_SIZE)
 def test_few_subcycles_full_size_fp64(name):
     _few_subcycles(name, 3, "fp64", TOL64)
 
 
-@pytest.mark.parametrize("name", ["256x256-dg2", "1024x1024-dg2", "2048x2048-dg2"])
+@pytest.mark.parametrize("name", FULL_SIZE)
 def test_few_subcycles_full_size_mixed(name):
     _few_subcycles(name, 3, "mixed", TOLMIX)
 
@@ -188,15 +192,45 @@ def test_equation_relaxation_form():
     assert max(field_errors(v0, S0, vr, Sr).values()) > 1e-6
 
 
+CONFIGS = [("two_phase", None), ("fused", (16, 16)), ("fused", (32, 14)),
+           ("persistent", (16, 14)), ("persistent", (16, 16)), ("persistent", (32, 14))]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("perturb", [0.0, 0.1])
-def test_fused_equals_two_phase(precision, perturb):
-    """Both launch strategies sum the nodal forces in the same order from the same
-    element computation: the results agree bitwise, over tile boundaries and
-    ragged tiles, for parallelogram and general cells, over several steps."""
+def test_launch_configs_agree_bitwise(precision, perturb):
+    """Every launch strategy and tile shape sums the nodal forces in the same
+    order from the same element computation: the results agree bitwise with
+    the default (fused, 16 x 14 tiles), over tile boundaries and ragged tiles,
+    for parallelogram and general cells, over several steps."""
     d = make_domain(173, 61, 6, 1, seed=61, h=2e3, perturb=perturb)
     state = random_state(d.nx, d.ny, d.n_s, seed=5)
-    a = gpu_run([d], 2, 25, precision=precision, states=[state], strategy="fused")[0]
-    b = gpu_run([d], 2, 25, precision=precision, states=[state], strategy="two_phase")[0]
-    log(f"fused vs two-phase {precision} perturb={perturb}: max |dv| {np.abs(a[0] - b[0]).max():.3e}")
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    ref = gpu_run([d], 2, 25, precision=precision, states=[state])[0]
+    for strategy, tile in CONFIGS:
+        got = gpu_run([d], 2, 25, precision=precision, states=[state], strategy=strategy,
+                      tile=tile)[0]
+        log(f"{strategy} {tile} vs fused (16, 14), {precision} perturb={perturb}: "
+            f"max |dv| {np.abs(got[0] - ref[0]).max():.3e}")
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (strategy, tile)
+
+
+def test_persistent_falls_back_for_mixed_cell_kinds():
+    """A batch with parallelogram and general domains needs two element kernels, so
+    the persistent strategy runs one launch per subcycle; results are unchanged."""
+    doms = [make_domain(40, 30, 6, 1, seed=1, h=4e3), make_domain(25, 33, 6, 1, seed=2, h=4e3,
+                                                                  perturb=0.1)]
+    a = gpu_run(doms, 2, 20, strategy="persistent")
+    b = gpu_run(doms, 2, 20, strategy="fused")
+    for (va, Sa), (vb, Sb) in zip(a, b):
+        assert np.array_equal(va, vb) and np.array_equal(Sa, Sb)
+
+
+def test_tile_shapes_need_one_ice_dof():
+    import paper_2402_00466_amd as M
+    ctx = M.Context([M.Domain(8, 8, 6, 3)])
+    with pytest.raises(M.MevpError):
+        ctx.set_config("fused", (16, 16))
+    with pytest.raises(M.MevpError):
+        ctx.set_config("fused", (15, 15))
+    ctx.set_config("persistent", (16, 14))
+    assert ctx.get_config() == ("persistent", (16, 14))

@@ -1,0 +1,96 @@
+"""GPU tests of the runtime around the kernels: graph replay of a time step,
+the autotuner and its cache, kernel timing."""
+import numpy as np
+import pytest
+
+from gpu_util import gpu_run, log
+from synth_inputs import make_domain, random_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_2402_00466_amd as M
+    M.lib()
+    return M
+
+
+def _ctx(M, d, **kw):
+    ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a)], **kw)
+    ctx.upload(0, d)
+    return ctx
+
+
+def _state(ctx):
+    v, S = ctx.get_state(0)
+    ctx.sync()
+    return v.cpu().numpy(), S.cpu().numpy()
+
+
+@pytest.mark.parametrize("n_sub", [10, 7])
+def test_graph_replays_match_eager(M, n_sub):
+    """Graph replay of mevp_step (even and odd n_sub: one or two captured graphs),
+    with eager work and host synchronisation between the replays: every step's
+    result equals the eagerly launched one bitwise; a parameter change in
+    between drops the graphs and is honoured."""
+    d = make_domain(50, 37, 6, 1, seed=11, h=3e3)
+    g = _ctx(M, d)
+    e = _ctx(M, d)
+    e.set_graph(False)
+    for k in range(5):
+        if k == 3:
+            for c in (g, e):
+                c.set_params(M.Params(alpha=250.0))
+        g.step(n_sub)
+        e.step(n_sub)
+        vg, Sg = _state(g)   # eager work + sync between replays
+        ve, Se = _state(e)
+        assert np.array_equal(vg, ve) and np.array_equal(Sg, Se), k
+    # eager subcycles on the graph context continue from the replayed state
+    g.subcycles(3)
+    e.subcycles(3)
+    assert all(np.array_equal(a, b) for a, b in zip(_state(g), _state(e)))
+
+
+def test_tune_keeps_state_and_result(M, tmp_path):
+    d = make_domain(64, 40, 6, 1, seed=12, h=2e3)
+    state = random_state(d.nx, d.ny, d.n_s, seed=3)
+    import torch
+    ctx = _ctx(M, d)
+    ctx.set_state(0, torch.as_tensor(state[0]).cuda(), torch.as_tensor(state[1]).cuda())
+    cache = tmp_path / "tune.txt"
+    strategy, tile = ctx.tune(n_trial=5, cache_path=str(cache))
+    log(f"tuned: {strategy} {tile}")
+    assert strategy in M.STRATEGIES and tuple(tile) in M.TILES
+    assert ctx.get_config() == (strategy, tuple(tile))
+    v, S = _state(ctx)
+    assert np.array_equal(v, state[0]) and np.array_equal(S, state[1])
+    ctx.step(20)
+    tuned = _state(ctx)
+    ref = gpu_run([d], 1, 20, states=[state])[0]
+    assert np.array_equal(tuned[0], ref[0]) and np.array_equal(tuned[1], ref[1])
+    # the cache answers without timing and names the same configuration
+    lines = cache.read_text().split("\n")
+    assert lines[0].startswith("gfx950/fp64/ns6/na1/dom1/el2560/max64x40 ")
+    ctx2 = _ctx(M, d)
+    assert ctx2.tune(n_trial=5, cache_path=str(cache)) == (strategy, tuple(tile))
+
+
+def test_timing_counts_launches(M):
+    d = make_domain(20, 20, 6, 1, seed=13, h=5e3)
+    ctx = _ctx(M, d)
+    ctx.timing_enable(64)
+    ctx.step(10)
+    t = ctx.timing_read()
+    assert t["element"][0] == 10 and t["begin_step"][0] == 1 and t["node"][0] == 0
+    assert t["element"][1] > 0
+    ctx.set_strategy("two_phase")
+    ctx.step(4)
+    t = ctx.timing_read()
+    assert t["element"][0] == 4 and t["node"][0] == 4
+    ctx.timing_enable(0)
