@@ -149,6 +149,10 @@ def measure(domains, precision, steps, warmup, n_sub, workload, strategy=None, t
     # launches of the subcycle kernel(s) in the timed region
     if strategy == "persistent":
         launches, per_launch, kernel = steps, n_sub, "k_fused (persistent: all subcycles of a step)"
+    elif strategy == "fused_pair":
+        pairs = (n_sub + 1) // 2  # an odd n_sub ends with one single-subcycle launch
+        launches, per_launch = steps * pairs, n_sub / pairs
+        kernel = "k_fused_pair (two subcycles per launch)"
     elif strategy == "two_phase":
         launches, per_launch, kernel = steps * n_sub, 1, "k_element + k_node (two-phase subcycle)"
     else:
@@ -261,7 +265,8 @@ def main():
     ap.add_argument("--n-sub", type=int, default=100)
     ap.add_argument("--workload", default="256x256-dg2")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--strategy", default=None, choices=["fused", "two_phase", "persistent"],
+    ap.add_argument("--strategy", default=None,
+                    choices=["fused", "two_phase", "persistent", "fused_pair"],
                     help="launch strategy; default: autotuned (mevp_tune) before the timed region")
     ap.add_argument("--tile", default=None, help="owned tile, e.g. 16x14 (with --strategy)")
     ap.add_argument("--no-variants", action="store_true")
@@ -277,8 +282,8 @@ def main():
     if args.record_traffic:
         key, fcsv, wcsv = args.record_traffic
         strategy = key.split("/")[2]
-        record_traffic(key, fcsv, wcsv, args.copy_mib,
-                       "k_element" if strategy == "two_phase" else "k_fused", args.record_command)
+        kern = {"two_phase": "k_element<", "fused_pair": "k_fused_pair<"}.get(strategy, "k_fused<")
+        record_traffic(key, fcsv, wcsv, args.copy_mib, kern, args.record_command)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the mEVP subcycle "
@@ -295,8 +300,10 @@ def main():
     M.lib()
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
     if args.traffic_probe:
-        traffic_probe(args.workload, args.precision, args.strategy or "fused",
-                      tile or (16, 14), args.n_sub if args.n_sub != 100 else 3, args.copy_mib)
+        strategy = args.strategy or "fused"
+        n_probe = 4 if strategy == "fused_pair" else 3  # whole launches of the kernel only
+        traffic_probe(args.workload, args.precision, strategy, tile or (16, 14),
+                      args.n_sub if args.n_sub != 100 else n_probe, args.copy_mib)
         return
 
     log(f"workload {args.workload} {args.precision}: generating inputs")
@@ -311,11 +318,14 @@ def main():
         other = "mixed" if args.precision == "fp64" else "fp64"
         plan = [(args.workload, other, args.steps, None, None),
                 (args.workload, args.precision, args.steps, "two_phase", None),
-                (args.workload, args.precision, args.steps, "fused", (16, 14)),
+                (args.workload, args.precision, args.steps, "fused", (16, 16)),
+                (args.workload, args.precision, args.steps, "fused_pair", (16, 16)),
                 (args.workload, args.precision, 3, "persistent", (16, 14)),
                 ("1024x1024-dg2", "fp64", 3, None, None), ("1024x1024-dg2", "mixed", 3, None, None),
                 ("2048x2048-dg2", "fp64", 3, None, None), ("2048x2048-dg2", "mixed", 3, None, None),
                 ("2048x2048-dg2", "fp64", 2, "two_phase", None),
+                ("2048x2048-dg2", "fp64", 2, "fused", (16, 14)),
+                ("2048x2048-dg2", "mixed", 2, "fused", (16, 14)),
                 ("batch64-dg2", "fp64", 2, None, None), ("batch64-dg2", "mixed", 2, None, None),
                 ("2048x2048-dg2-bilinear", "fp64", 2, None, None),
                 ("2048x2048-dg2-bilinear", "mixed", 2, None, None),

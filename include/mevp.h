@@ -105,14 +105,20 @@ typedef struct {
  * subcycles). Used when all domains take the same element kernel; otherwise,
  * or if the device cannot hold the grid, it falls back to FUSED.
  * TWO_PHASE: an element launch writing the element forces to the workspace,
- * then a node launch gathering them. */
+ * then a node launch gathering them.
+ * FUSED_PAIR: two subcycles per launch on the FUSED tiles (temporal
+ * blocking): each workgroup recomputes a halo of two elements, keeps the
+ * intermediate velocity in LDS and the intermediate stress in registers, so
+ * v and S cross HBM once per two subcycles; an odd count ends with one FUSED
+ * launch. */
 typedef enum {
   MEVP_STRATEGY_FUSED = 0,
   MEVP_STRATEGY_TWO_PHASE = 1,
-  MEVP_STRATEGY_PERSISTENT = 2
+  MEVP_STRATEGY_PERSISTENT = 2,
+  MEVP_STRATEGY_FUSED_PAIR = 3
 } mevp_strategy;
 
-/* Launch configuration: strategy and the fused kernel's tile of owned
+/* Launch configuration: strategy and the fused kernels' tile of owned
  * elements per workgroup (16 x 14; with n_a = 1 also 16 x 16 and 32 x 14). */
 typedef struct {
   int strategy;  /* a mevp_strategy */

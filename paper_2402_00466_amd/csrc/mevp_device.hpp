@@ -162,29 +162,35 @@ __device__ __forceinline__ void vp_stress(const KParams &p, double P, T e11, T e
   s22 = tPD * (T(0.625) * e22 + T(0.375) * e11) - thP;
 }
 
-// Velocities of the 9 local nodes of element (ex, ey). In float they are
-// taken relative to local node 0 before narrowing (the gradient of a constant
-// is zero), which keeps the strain free of cancellation.
+// Velocities of the 9 local nodes of an element whose first node is j0 in
+// arrays vxs, vys of row stride `stride` (global memory or LDS). In float
+// they are taken relative to local node 0 before narrowing (the gradient of a
+// constant is zero), which keeps the strain free of cancellation.
 template <class T>
-__device__ __forceinline__ void load_velocity(const DomDev &D, const double *v, int ex, int ey,
-                                              T (&vx)[9], T (&vy)[9]) {
-  const double *vxg = v + 2 * (size_t)D.node_off;
-  const double *vyg = vxg + D.nn;
-  const int NX = 2 * D.nx + 1;
-  const int j0 = 2 * ey * NX + 2 * ex;
+__device__ __forceinline__ void gather_velocity(const double *vxs, const double *vys, int j0,
+                                                int stride, T (&vx)[9], T (&vy)[9]) {
   double bx = 0.0, by = 0.0;
   if (sizeof(T) < sizeof(double)) {
-    bx = vxg[j0];
-    by = vyg[j0];
+    bx = vxs[j0];
+    by = vys[j0];
   }
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const int j = j0 + b * NX + c;
-      vx[3 * b + c] = T(vxg[j] - bx);
-      vy[3 * b + c] = T(vyg[j] - by);
+      const int j = j0 + b * stride + c;
+      vx[3 * b + c] = T(vxs[j] - bx);
+      vy[3 * b + c] = T(vys[j] - by);
     }
+}
+
+// the same for element (ex, ey) of a domain, from the global v array
+template <class T>
+__device__ __forceinline__ void load_velocity(const DomDev &D, const double *v, int ex, int ey,
+                                              T (&vx)[9], T (&vy)[9]) {
+  const double *vxg = v + 2 * (size_t)D.node_off;
+  const int NX = 2 * D.nx + 1;
+  gather_velocity<T>(vxg, vxg + D.nn, 2 * ey * NX + 2 * ex, NX, vx, vy);
 }
 
 template <int NA>
@@ -198,16 +204,18 @@ __device__ __forceinline__ void load_ice(const DevArrays &d, const DomDev &D, in
   }
 }
 
-// Relaxation of Listing 1: R <- fac S_in + ainv R (R holds Pi_e(s) on entry).
-template <int NS, class T, class TS>
-__device__ __forceinline__ void relax(const TS *S_in, size_t ne, int el, const KParams &p,
-                                      T (&R11)[NS], T (&R12)[NS], T (&R22)[NS]) {
+// Relaxation of Listing 1: R <- fac S_old + ainv R (R holds Pi_e(s) on entry);
+// sold(c, k) is coefficient k of stress component c (11, 12, 22) before the
+// update, in T.
+template <int NS, class T, class SOld>
+__device__ __forceinline__ void relax(const KParams &p, SOld sold, T (&R11)[NS], T (&R12)[NS],
+                                      T (&R22)[NS]) {
   const T fac = T(p.fac), ainv = T(p.ainv);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    R11[k] = fac * T(S_in[(0 * NS + k) * ne + el]) + ainv * R11[k];
-    R12[k] = fac * T(S_in[(1 * NS + k) * ne + el]) + ainv * R12[k];
-    R22[k] = fac * T(S_in[(2 * NS + k) * ne + el]) + ainv * R22[k];
+    R11[k] = fac * sold(0, k) + ainv * R11[k];
+    R12[k] = fac * sold(1, k) + ainv * R12[k];
+    R22[k] = fac * sold(2, k) + ainv * R22[k];
   }
 }
 
@@ -238,6 +246,40 @@ struct DomBufs {
 };
 
 // ---------------------------------------------------------------------------
+// Geometry of one element as the element update needs it: the constant
+// Jacobian of a parallelogram cell, or the bilinear map of a general cell.
+// ---------------------------------------------------------------------------
+template <class T, bool AFF>
+struct Geo;
+template <class T>
+struct Geo<T, true> {
+  T J00, J01, J10, J11;
+};
+template <class T>
+struct Geo<T, false> {
+  Cell<T> cell;
+};
+
+template <class T, bool AFF>
+__device__ __forceinline__ Geo<T, AFF> load_geo(const DevArrays &d, const DomDev &D, int ex,
+                                                int ey) {
+  if constexpr (AFF) {
+    const double *VX = d.vert + 2 * (size_t)D.vert_off;
+    const double *VY = VX + D.nv;
+    const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
+    const double X0 = VX[i0], Y0 = VY[i0];
+    Geo<T, true> g;
+    g.J00 = T(VX[i0 + 1] - X0);
+    g.J10 = T(VY[i0 + 1] - Y0);
+    g.J01 = T(VX[i2] - X0);
+    g.J11 = T(VY[i2] - Y0);
+    return g;
+  } else {
+    return Geo<T, false>{load_cell<T>(D, d.vert, ex, ey)};
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Element update, parallelogram cells: strain -> stress update -> nodal forces.
 // J = [[J00, J01], [J10, J11]] is constant, |J| cancels from the projections
 // (M_e = |J| diag(int psi_k^2)), and
@@ -245,32 +287,22 @@ struct DomBufs {
 //   divergence:            f_x[a] = -(J11 (Axi^T S11)[a] - J01 (Axi^T S12)[a]
 //                                     + J00 (Aeta^T S12)[a] - J10 (Aeta^T S11)[a])
 // with the exact reference operators a_xi, a_eta of mevp_ref.hpp.
-// On return R holds the new stress coefficients and fx, fy the forces.
+// Inputs: the geometry, the ice fields, the 9 nodal velocities and sold(c, k)
+// (the stress before the update). On return R holds the new stress
+// coefficients and fx, fy the forces.
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class TS>
-__device__ __forceinline__ void element_affine(const DevArrays &d, const DomDev &D,
-                                               const KParams &p, const double *v_in,
-                                               const TS *S_in, int el, int ex, int ey,
+template <int NS, int NA, class T, class SOld>
+__device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, true> &g,
+                                               const double (&Hc)[NA], const double (&Ac)[NA],
+                                               const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                T (&fx)[9], T (&fy)[9]) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
-  T J00, J01, J10, J11;
-  {
-    const double *VX = d.vert + 2 * (size_t)D.vert_off;
-    const double *VY = VX + D.nv;
-    const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
-    const double X0 = VX[i0], Y0 = VY[i0];
-    J00 = T(VX[i0 + 1] - X0);
-    J10 = T(VY[i0 + 1] - Y0);
-    J01 = T(VX[i2] - X0);
-    J11 = T(VY[i2] - Y0);
-  }
+  const T J00 = g.J00, J01 = g.J01, J10 = g.J10, J11 = g.J11;
   const T idet = T(1) / (J00 * J11 - J01 * J10);
 
   // ---- strain ----
-  T vx[9], vy[9];
-  load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
   T E11[NS], E12[NS], E22[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -293,8 +325,6 @@ __device__ __forceinline__ void element_affine(const DevArrays &d, const DomDev 
   }
 
   // ---- stress update ----
-  double Hc[NA], Ac[NA];
-  load_ice<NA>(d, D, el, Hc, Ac);
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
@@ -323,7 +353,7 @@ __device__ __forceinline__ void element_affine(const DevArrays &d, const DomDev 
       }
     }
   }
-  relax<NS, T, TS>(S_in, (size_t)D.ne, el, p, R11, R12, R22);
+  relax<NS, T>(p, sold, R11, R12, R22);
 
   // ---- divergence, element part ----
 #pragma unroll
@@ -351,23 +381,22 @@ __device__ __forceinline__ void element_affine(const DevArrays &d, const DomDev 
 
 // ---------------------------------------------------------------------------
 // Element update, general bilinear cells: Jacobian per Gauss point, local
-// mass matrix M_e = Psi W_e Psi^T factorised per element.
+// mass matrix M_e = Psi W_e Psi^T factorised per element. Same inputs and
+// outputs as element_affine.
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class TS>
-__device__ __forceinline__ void element_general(const DevArrays &d, const DomDev &D,
-                                                const KParams &p, const double *v_in,
-                                                const TS *S_in, int el, int ex, int ey,
+template <int NS, int NA, class T, class SOld>
+__device__ __forceinline__ void element_general(const KParams &p, const Geo<T, false> &g,
+                                                const double (&Hc)[NA], const double (&Ac)[NA],
+                                                const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                 T (&fx)[9], T (&fy)[9]) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
-  const Cell<T> cell = load_cell<T>(D, d.vert, ex, ey);
+  const Cell<T> &cell = g.cell;
   Ldl<NS, T> mass;
   mass.template build<Q>(cell);
 
   // ---- strain ----
-  T vx[9], vy[9];
-  load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
   T E11[NS], E12[NS], E22[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) E11[k] = E12[k] = E22[k] = T(0);
@@ -407,8 +436,6 @@ __device__ __forceinline__ void element_general(const DevArrays &d, const DomDev
   mass.solve(E22);
 
   // ---- stress update ----
-  double Hc[NA], Ac[NA];
-  load_ice<NA>(d, D, el, Hc, Ac);
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
@@ -443,7 +470,7 @@ __device__ __forceinline__ void element_general(const DevArrays &d, const DomDev
   mass.solve(R11);
   mass.solve(R12);
   mass.solve(R22);
-  relax<NS, T, TS>(S_in, (size_t)D.ne, el, p, R11, R12, R22);
+  relax<NS, T>(p, sold, R11, R12, R22);
 
   // ---- divergence, element part: f[a] = -sum_q w_q |J_q| sigma(q) grad phi_a(q)
   //      = -sum_q (dphi_a/dxi Gxi + dphi_a/deta Geta) with G = w_q sigma adj(J)^T ----
@@ -482,16 +509,34 @@ __device__ __forceinline__ void element_general(const DevArrays &d, const DomDev
   }
 }
 
+template <int NS, int NA, class T, bool AFF, class SOld>
+__device__ __forceinline__ void element_compute(const KParams &p, const Geo<T, AFF> &g,
+                                                const double (&Hc)[NA], const double (&Ac)[NA],
+                                                const T (&vx)[9], const T (&vy)[9], SOld sold,
+                                                T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
+                                                T (&fx)[9], T (&fy)[9]) {
+  if constexpr (AFF)
+    element_affine<NS, NA, T>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+  else
+    element_general<NS, NA, T>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+}
+
+// Element update of element el = (ex, ey) with every input read from global
+// memory (v and S of the current subcycle).
 template <int NS, int NA, class T, class TS, bool AFF>
 __device__ __forceinline__ void element_update(const DevArrays &d, const DomDev &D,
                                                const KParams &p, const double *v_in,
                                                const TS *S_in, int el, int ex, int ey,
                                                T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                T (&fx)[9], T (&fy)[9]) {
-  if constexpr (AFF)
-    element_affine<NS, NA, T, TS>(d, D, p, v_in, S_in, el, ex, ey, R11, R12, R22, fx, fy);
-  else
-    element_general<NS, NA, T, TS>(d, D, p, v_in, S_in, el, ex, ey, R11, R12, R22, fx, fy);
+  const Geo<T, AFF> g = load_geo<T, AFF>(d, D, ex, ey);
+  T vx[9], vy[9];
+  load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
+  double Hc[NA], Ac[NA];
+  load_ice<NA>(d, D, el, Hc, Ac);
+  const size_t ne = (size_t)D.ne;
+  auto sold = [&](int c, int k) { return T(S_in[(c * NS + k) * ne + el]); };
+  element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
 // Velocity update of one interior node:
@@ -603,6 +648,69 @@ __global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p, Buf
 }
 
 // ---------------------------------------------------------------------------
+// Node part of a tile: the velocity update of the CG2 nodes (ix, iy) in
+// [ix0, ix1) x [iy0, iy1) of one domain, row-major (consecutive lanes,
+// consecutive nodes), each lane taking up to R of them and issuing all their
+// loads before the first update. The forces of element (ex, ey) are at
+// fl[.][(ey - ey0) * FW + ex - ex0] (every element around an interior node of
+// the range must be there); each interior node sums them in ascending element
+// order. uin(ix, iy, j, ux, uy) reads v^{p-1} of node j = iy * NX + ix,
+// out(ix, iy, j, vx, vy) stores v^p; boundary nodes get v = 0 (Dirichlet).
+// ---------------------------------------------------------------------------
+template <int R, int NT, int NF, int FW, class T, class UIn, class Out>
+__device__ __forceinline__ void update_nodes(const KParams &p, const DomDev &D, const double *nc,
+                                             int ix0, int ix1, int iy0, int iy1, int ex0, int ey0,
+                                             const T (*fl)[NF], UIn uin, Out out) {
+  const int tid = (int)threadIdx.x;
+  const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
+  const size_t nn = (size_t)D.nn;
+  const int w = ix1 - ix0, n = w * (iy1 - iy0);
+  int jn[R], ixs[R], iys[R];
+  bool act[R], bnd[R];
+  double ux[R], uy[R], o[R][6];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int k = tid + m * NT;
+    act[m] = k < n;
+    ixs[m] = ix0 + (act[m] ? k % w : 0);
+    iys[m] = iy0 + (act[m] ? k / w : 0);
+    jn[m] = iys[m] * NX + ixs[m];
+    bnd[m] = ixs[m] == 0 || iys[m] == 0 || ixs[m] == NX - 1 || iys[m] == NY - 1;
+    if (act[m] && !bnd[m]) {
+      uin(ixs[m], iys[m], jn[m], ux[m], uy[m]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[m][c] = nc[c * nn + jn[m]];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    if (!act[m]) continue;
+    if (bnd[m]) {
+      out(ixs[m], iys[m], jn[m], 0.0, 0.0);
+      continue;
+    }
+    const int ix = ixs[m], iy = iys[m];
+    const int ney = (iy & 1) ? 1 : 2, nex = (ix & 1) ? 1 : 2;
+    const int ey_first = (iy & 1) ? (iy - 1) / 2 : iy / 2 - 1;
+    const int ex_first = (ix & 1) ? (ix - 1) / 2 : ix / 2 - 1;
+    const int b0 = (iy & 1) ? 1 : 2, c0 = (ix & 1) ? 1 : 2;
+    double Fx = 0.0, Fy = 0.0;
+    for (int tt = 0; tt < ney; ++tt) {
+      const int ly = ey_first + tt - ey0, bb = b0 - 2 * tt;
+      for (int ss = 0; ss < nex; ++ss) {
+        const int lx = ex_first + ss - ex0, c = c0 - 2 * ss;
+        const int a = 3 * bb + c, le = ly * FW + lx;
+        Fx += (double)fl[a][le];
+        Fy += (double)fl[9 + a][le];
+      }
+    }
+    double vx, vy;
+    velocity_update6(p, o[m], ux[m], uy[m], Fx, Fy, vx, vy);
+    out(ix, iy, jn[m], vx, vy);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused subcycle on one tile of EX x EY elements. The tile's first column
 // and row are a halo (the elements left of and below the owned
 // (EX-1) x (EY-1) block): their forces are recomputed here (their stress is
@@ -637,62 +745,139 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
     }
   }
   __syncthreads();
-  // ---- nodes owned by the tile, row-major (consecutive lanes, consecutive
-  // nodes); each lane takes up to R of them and issues all their loads before
-  // the first update ----
+  // ---- nodes owned by the tile ----
   const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
   const size_t nn = (size_t)D.nn;
-  const double *nc = d.nc + (size_t)6 * D.node_off;
   const int ix0 = 2 * t.x0, iy0 = 2 * t.y0;
   const int ix1 = (t.x0 + TX >= D.nx) ? NX : ix0 + 2 * TX;
   const int iy1 = (t.y0 + TY >= D.ny) ? NY : iy0 + 2 * TY;
-  const int w = ix1 - ix0, n = w * (iy1 - iy0);
   constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;
-  int jn[R], ixs[R], iys[R];
-  bool act[R], bnd[R];
-  double ux[R], uy[R], o[R][6];
+  auto uin = [&](int, int, int j, double &ux, double &uy) {
+    ux = B.v_in[j];
+    uy = B.v_in[nn + j];
+  };
+  auto out = [&](int, int, int j, double vx, double vy) {
+    B.v_out[j] = vx;
+    B.v_out[nn + j] = vy;
+  };
+  update_nodes<R, NT, NT, EX, T>(p, D, d.nc + (size_t)6 * D.node_off, ix0, ix1, iy0, iy1,
+                                 t.x0 - 1, t.y0 - 1, fl, uin, out);
+}
+
+// ---------------------------------------------------------------------------
+// Two subcycles on one tile in one pass (temporal blocking). The tile of
+// owned (EX-1) x (EY-1) elements (the same tiles as fused_tile) takes a halo
+// of two elements on its low sides and one on its high sides:
+//   A  elements [x0-2, x0+TX] x [y0-2, y0+TY] (one per lane): element update
+//      from v^{p-1}, S^{p-1} in global memory; forces to LDS, the new stress
+//      kept in registers;
+//   B  nodes [2x0-2, 2x0+2TX] x [...]: velocity update to v^p, kept in LDS;
+//   C  elements [x0-1, x0+TX-1] x [...] (the same lanes): element update from
+//      v^p in LDS and S^p in registers; S^{p+1} of the owned elements stored;
+//   D  the owned nodes: velocity update from v^p in LDS to v^{p+1}, stored.
+// Every element and node update is the same arithmetic as in fused_tile, so
+// two passes of this kernel equal four single subcycles bit for bit. Only
+// v^{p-1} / S^{p-1} are read and only v^{p+1} / S^{p+1} written (double
+// buffering as in fused_tile).
+// ---------------------------------------------------------------------------
+template <int NS, int NA, class T, class TS, bool AFF, int EX, int EY>
+__global__ void __launch_bounds__((EX + 2) * (EY + 2))
+    k_fused_pair(DevArrays d, KParams p, const Tile *tiles, Bufs b) {
+  constexpr int TX = EX - 1, TY = EY - 1;
+  constexpr int FX = EX + 2, FY = EY + 2, NT = FX * FY;  // phase A elements = lanes
+  constexpr int VW = 2 * EX + 1, VH = 2 * EY + 1;         // phase B nodes
+  __shared__ T fl[18][NT];
+  __shared__ double vl[2][VW * VH];
+  const Tile t = tiles[blockIdx.x];
+  const DomDev D = d.doms[t.dom];
+  const DomBufs<TS> B(b, D, NS);
+  const int tid = (int)threadIdx.x;
+  const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
+  const size_t nn = (size_t)D.nn, ne = (size_t)D.ne;
+  const double *nc = d.nc + (size_t)6 * D.node_off;
+  const int lx = tid % FX, ly = tid / FX;
+  const int ex = t.x0 - 2 + lx, ey = t.y0 - 2 + ly;
+  const bool in1 = ex >= 0 && ey >= 0 && ex < D.nx && ey < D.ny;
+  const int el = in1 ? ey * D.nx + ex : 0;
+
+  // ---- A ----
+  Geo<T, AFF> g{};
+  double Hc[NA], Ac[NA];
+  T S11[NS], S12[NS], S22[NS];  // S^p, as stored (rounded to TS)
+  if (in1) {
+    g = load_geo<T, AFF>(d, D, ex, ey);
+    T vx[9], vy[9];
+    load_velocity<T>(D, B.v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
+    load_ice<NA>(d, D, el, Hc, Ac);
+    auto sold = [&](int c, int k) { return T(B.S_in[(c * NS + k) * ne + el]); };
+    T fx[9], fy[9];
+    element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, S11, S12, S22, fx, fy);
 #pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const int k = tid + m * NT;
-    act[m] = k < n;
-    ixs[m] = ix0 + (act[m] ? k % w : 0);
-    iys[m] = iy0 + (act[m] ? k / w : 0);
-    jn[m] = iys[m] * NX + ixs[m];
-    bnd[m] = ixs[m] == 0 || iys[m] == 0 || ixs[m] == NX - 1 || iys[m] == NY - 1;
-    if (act[m] && !bnd[m]) {
-      ux[m] = B.v_in[jn[m]];
-      uy[m] = B.v_in[nn + jn[m]];
+    for (int k = 0; k < NS; ++k) {
+      S11[k] = T(TS(S11[k]));
+      S12[k] = T(TS(S12[k]));
+      S22[k] = T(TS(S22[k]));
+    }
 #pragma unroll
-      for (int c = 0; c < 6; ++c) o[m][c] = nc[c * nn + jn[m]];
+    for (int a = 0; a < 9; ++a) {
+      fl[a][tid] = fx[a];
+      fl[9 + a][tid] = fy[a];
     }
   }
+  __syncthreads();
+
+  // ---- B: v^p on the nodes of the phase C elements, into LDS ----
+  {
+    const int jx0 = 2 * t.x0 - 2, jy0 = 2 * t.y0 - 2;  // LDS origin
+    const int ix0 = max(jx0, 0), iy0 = max(jy0, 0);
+    const int ix1 = min(jx0 + VW, NX), iy1 = min(jy0 + VH, NY);
+    constexpr int R = (VW * VH + NT - 1) / NT;
+    auto uin = [&](int, int, int j, double &ux, double &uy) {
+      ux = B.v_in[j];
+      uy = B.v_in[nn + j];
+    };
+    auto out = [&](int ix, int iy, int, double vx, double vy) {
+      const int q = (iy - jy0) * VW + (ix - jx0);
+      vl[0][q] = vx;
+      vl[1][q] = vy;
+    };
+    update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, t.x0 - 2, t.y0 - 2, fl, uin, out);
+  }
+  __syncthreads();
+
+  // ---- C ----
+  if (in1 && lx >= 1 && ly >= 1 && lx <= EX && ly <= EY) {
+    T vx[9], vy[9];
+    gather_velocity<T>(vl[0], vl[1], (2 * ly - 2) * VW + 2 * lx - 2, VW, vx, vy);
+    auto sold = [&](int c, int k) { return c == 0 ? S11[k] : c == 1 ? S12[k] : S22[k]; };
+    T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
+    element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+    if (lx >= 2 && ly >= 2) store_stress<NS, T, TS>(B.S_out, ne, el, R11, R12, R22);
 #pragma unroll
-  for (int m = 0; m < R; ++m) {
-    if (!act[m]) continue;
-    if (bnd[m]) {
-      B.v_out[jn[m]] = 0.0;
-      B.v_out[nn + jn[m]] = 0.0;
-      continue;
+    for (int a = 0; a < 9; ++a) {
+      fl[a][tid] = fx[a];
+      fl[9 + a][tid] = fy[a];
     }
-    const int ix = ixs[m], iy = iys[m];
-    const int ney = (iy & 1) ? 1 : 2, nex = (ix & 1) ? 1 : 2;
-    const int ey0 = (iy & 1) ? (iy - 1) / 2 : iy / 2 - 1;
-    const int ex0 = (ix & 1) ? (ix - 1) / 2 : ix / 2 - 1;
-    const int b0 = (iy & 1) ? 1 : 2, c0 = (ix & 1) ? 1 : 2;
-    double Fx = 0.0, Fy = 0.0;
-    for (int tt = 0; tt < ney; ++tt) {
-      const int ly = ey0 + tt - t.y0 + 1, bb = b0 - 2 * tt;
-      for (int ss = 0; ss < nex; ++ss) {
-        const int lx = ex0 + ss - t.x0 + 1, c = c0 - 2 * ss;
-        const int a = 3 * bb + c, le = ly * EX + lx;
-        Fx += (double)fl[a][le];
-        Fy += (double)fl[9 + a][le];
-      }
-    }
-    double vx, vy;
-    velocity_update6(p, o[m], ux[m], uy[m], Fx, Fy, vx, vy);
-    B.v_out[jn[m]] = vx;
-    B.v_out[nn + jn[m]] = vy;
+  }
+  __syncthreads();
+
+  // ---- D: the owned nodes, v^{p+1} to global memory ----
+  {
+    const int jx0 = 2 * t.x0 - 2, jy0 = 2 * t.y0 - 2;
+    const int ix0 = 2 * t.x0, iy0 = 2 * t.y0;
+    const int ix1 = (t.x0 + TX >= D.nx) ? NX : ix0 + 2 * TX;
+    const int iy1 = (t.y0 + TY >= D.ny) ? NY : iy0 + 2 * TY;
+    constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;
+    auto uin = [&](int ix, int iy, int, double &ux, double &uy) {
+      const int q = (iy - jy0) * VW + (ix - jx0);
+      ux = vl[0][q];
+      uy = vl[1][q];
+    };
+    auto out = [&](int, int, int j, double vx, double vy) {
+      B.v_out[j] = vx;
+      B.v_out[nn + j] = vy;
+    };
+    update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, t.x0 - 2, t.y0 - 2, fl, uin, out);
   }
 }
 
@@ -1027,10 +1212,16 @@ inline hipError_t two_phase_t(const DevArrays &d, const KParams &p, const Launch
   return hipGetLastError();
 }
 
-// Fused subcycle(s): tile kernel(s), parallelogram tiles first.
+// Fused subcycle(s): tile kernel(s), parallelogram tiles first; f.pair: the
+// two-subcycle kernel.
 template <int NS, int NA, class T, bool AFF, int EX, int EY>
 inline hipError_t fused_one(const DevArrays &d, const KParams &p, const Tile *tiles, int ntiles,
                             const FusedArgs &f, hipStream_t s) {
+  if (f.pair) {
+    hipLaunchKernelGGL((k_fused_pair<NS, NA, T, T, AFF, EX, EY>), dim3(ntiles),
+                       dim3((EX + 2) * (EY + 2)), 0, s, d, p, tiles, f.b0);
+    return hipGetLastError();
+  }
   auto kern = k_fused<NS, NA, T, T, AFF, EX, EY>;
   if (!f.persist) {
     hipLaunchKernelGGL(kern, dim3(ntiles), dim3(EX * EY), 0, s, d, p, tiles, ntiles, f.b0, f.b1, 1, 0);

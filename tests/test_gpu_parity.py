@@ -55,7 +55,7 @@ WHOLE_RUNS = [
 ]
 
 
-@pytest.mark.parametrize("strategy", ["fused", "two_phase", "persistent"])
+@pytest.mark.parametrize("strategy", ["fused", "two_phase", "persistent", "fused_pair"])
 @pytest.mark.parametrize("case", WHOLE_RUNS, ids=lambda c: "x".join(map(str, c[:4])))
 def test_whole_run_fp64(case, strategy):
     nx, ny, ns, na, h, pert, ho, steps, nsub = case
@@ -81,11 +81,12 @@ def test_whole_run_32x32_dg1_workload():
     _assert_close(field_errors(vm, Sm, vr, Sr), TOLMIX, "32x32-dg1 mixed")
 
 
-def test_whole_run_mixed_small():
+@pytest.mark.parametrize("strategy", ["fused", "fused_pair"])
+def test_whole_run_mixed_small(strategy):
     d = make_domain(40, 23, 6, 3, seed=7, h=12e3, perturb=0.15, ho_amp=0.3)
-    (v, S), = gpu_run([d], 2, 30, precision="mixed")
-    vr, Sr = oracle_run(d, 2, 30)
-    _assert_close(field_errors(v, S, vr, Sr), TOLMIX, "mixed 40x23")
+    (v, S), = gpu_run([d], 2, 31, precision="mixed", strategy=strategy)
+    vr, Sr = oracle_run(d, 2, 31)
+    _assert_close(field_errors(v, S, vr, Sr), TOLMIX, f"mixed 40x23 {strategy}")
 
 
 def _few_subcycles(name, n_sub, precision, tol, dom_index=0):
@@ -193,7 +194,8 @@ def test_equation_relaxation_form():
 
 
 CONFIGS = [("two_phase", None), ("fused", (16, 16)), ("fused", (32, 14)),
-           ("persistent", (16, 14)), ("persistent", (16, 16)), ("persistent", (32, 14))]
+           ("persistent", (16, 14)), ("persistent", (16, 16)), ("persistent", (32, 14)),
+           ("fused_pair", (16, 14)), ("fused_pair", (16, 16)), ("fused_pair", (32, 14))]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -212,6 +214,29 @@ def test_launch_configs_agree_bitwise(precision, perturb):
         log(f"{strategy} {tile} vs fused (16, 14), {precision} perturb={perturb}: "
             f"max |dv| {np.abs(got[0] - ref[0]).max():.3e}")
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (strategy, tile)
+
+
+PAIR_FULL = [("256x256-dg2", "fp64"), ("256x256-dg2", "mixed"), ("2048x2048-dg2", "fp64"),
+             ("2048x2048-dg2", "mixed"), ("2048x2048-dg2-bilinear", "fp64"),
+             ("batch64-dg2", "fp64"), ("batch64-dg2", "mixed")]
+
+
+@pytest.mark.parametrize("name,precision", PAIR_FULL)
+def test_pair_kernel_bitwise_at_full_size(name, precision):
+    """Two subcycles per launch (every tile shape) against one per launch, at the
+    benchmark sizes, from a seeded state: 5 subcycles (two pair launches and a
+    single one) agree bit for bit; the single-subcycle kernel is itself checked
+    against the oracle at these sizes (test_few_subcycles_full_size_*)."""
+    doms = named_workload(name)
+    states = [random_state(d.nx, d.ny, d.n_s, seed=99 + k) for k, d in enumerate(doms)]
+    ref = gpu_run(doms, 1, 5, precision=precision, states=states)
+    tiles = [(16, 14)] + ([(16, 16), (32, 14)] if doms[0].n_a == 1 else [])
+    for tile in tiles:
+        log(f"workload {name} {precision}: fused_pair {tile} vs fused (16, 14), 5 subcycles")
+        got = gpu_run(doms, 1, 5, precision=precision, states=states, strategy="fused_pair",
+                      tile=tile)
+        for k, ((v, S), (vr, Sr)) in enumerate(zip(got, ref)):
+            assert np.array_equal(v, vr) and np.array_equal(S, Sr), (tile, k)
 
 
 def test_persistent_falls_back_for_mixed_cell_kinds():

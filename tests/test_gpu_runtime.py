@@ -32,15 +32,16 @@ def _state(ctx):
     return v.cpu().numpy(), S.cpu().numpy()
 
 
+@pytest.mark.parametrize("strategy", ["fused", "fused_pair"])
 @pytest.mark.parametrize("n_sub", [10, 7])
-def test_graph_replays_match_eager(M, n_sub):
+def test_graph_replays_match_eager(M, n_sub, strategy):
     """Graph replay of mevp_step (even and odd n_sub: one or two captured graphs),
     with eager work and host synchronisation between the replays: every step's
     result equals the eagerly launched one bitwise; a parameter change in
     between drops the graphs and is honoured."""
     d = make_domain(50, 37, 6, 1, seed=11, h=3e3)
-    g = _ctx(M, d)
-    e = _ctx(M, d)
+    g = _ctx(M, d, strategy=strategy)
+    e = _ctx(M, d, strategy=strategy)
     e.set_graph(False)
     for k in range(5):
         if k == 3:
