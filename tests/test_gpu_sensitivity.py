@@ -1,0 +1,71 @@
+"""Whole time steps on the 256 x 256 benchmark mesh (2 km cells), against the
+oracle's own sensitivity.
+
+At 2 km the mEVP iteration (alpha = beta = 300) amplifies a rounding-level
+change by ~1e9 over the 100 subcycles of a step: the oracle itself, fed H
+perturbed by 1e-15 relative noise, moves by ~1e-7 (normwise). No two
+independently rounded programs can agree to 1e-12 there, so the whole-step
+check at this size compares the GPU's distance from the oracle with the
+oracle's distance from itself under such perturbations (the noise floor),
+field by field. FP64: perturbations of 1e-15 relative; mixed precision:
+1e-7 (float rounding). Exact agreement at these sizes is checked over a few
+subcycles in test_gpu_parity.py, where the amplification is bounded.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import field_errors, gpu_run, log, oracle_run
+from synth_inputs import named_workload
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("vx", "vy", "S11", "S12", "S22")
+MARGIN = 10.0  # GPU error allowed, in units of the largest floor sample
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    import paper_2402_00466_amd as M
+    M.lib()
+    d, = named_workload("256x256-dg2")
+    ref = oracle_run(d, 1, 100)
+    return d, ref, {}
+
+
+def _floor(d, ref, cache, eps):
+    """Per field, the largest normwise change of the oracle's result over three
+    perturbations of H by eps relative noise."""
+    if eps not in cache:
+        import copy
+        fl = dict.fromkeys(FIELDS, 0.0)
+        for seed in range(3):
+            dp = copy.copy(d)
+            rng = np.random.default_rng(seed)
+            dp.H = d.H * (1.0 + eps * rng.standard_normal(d.H.shape))
+            e = field_errors(*oracle_run(dp, 1, 100), *ref)
+            fl = {k: max(fl[k], e[k]) for k in FIELDS}
+        cache[eps] = fl
+    return cache[eps]
+
+
+@pytest.mark.parametrize("precision,strategy,tile,eps", [
+    ("fp64", "fused", (16, 14), 1e-15),
+    ("fp64", "fused_pair", (16, 16), 1e-15),
+    ("mixed", "fused_pair", (16, 16), 1e-7),
+])
+def test_whole_step_256_within_oracle_noise_floor(setup, precision, strategy, tile, eps):
+    d, ref, cache = setup
+    floor = _floor(d, ref, cache, eps)
+    log(f"256x256-dg2, 1 step x 100 subcycles, {precision} {strategy} {tile}")
+    (v, S), = gpu_run([d], 1, 100, precision=precision, strategy=strategy, tile=tile)
+    err = field_errors(v, S, *ref)
+    log("  gpu vs oracle: " + " ".join(f"{k}={err[k]:.2e}" for k in FIELDS))
+    log(f"  oracle floor (H x (1 + {eps:g} noise)): " +
+        " ".join(f"{k}={floor[k]:.2e}" for k in FIELDS))
+    assert np.abs(ref[0]).max() > 1e-3  # the ice moved
+    bad = {k: (err[k], floor[k]) for k in FIELDS if not err[k] <= MARGIN * floor[k]}
+    assert not bad, f"above {MARGIN:g} x the oracle's noise floor: {bad}"
