@@ -149,10 +149,11 @@ def measure(domains, precision, steps, warmup, n_sub, workload, strategy=None, t
     # launches of the subcycle kernel(s) in the timed region
     if strategy == "persistent":
         launches, per_launch, kernel = steps, n_sub, "k_fused (persistent: all subcycles of a step)"
-    elif strategy == "fused_pair":
-        pairs = (n_sub + 1) // 2  # an odd n_sub ends with one single-subcycle launch
-        launches, per_launch = steps * pairs, n_sub / pairs
-        kernel = "k_fused_pair (two subcycles per launch)"
+    elif strategy in ("fused_pair", "fused_triple"):
+        depth = 2 if strategy == "fused_pair" else 3
+        per_step = (n_sub + depth - 1) // depth  # a remainder ends the step in one launch
+        launches, per_launch = steps * per_step, n_sub / per_step
+        kernel = f"k_fused_multi (K = {depth} subcycles per launch)"
     elif strategy == "two_phase":
         launches, per_launch, kernel = steps * n_sub, 1, "k_element + k_node (two-phase subcycle)"
     else:
@@ -266,7 +267,7 @@ def main():
     ap.add_argument("--workload", default="256x256-dg2")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--strategy", default=None,
-                    choices=["fused", "two_phase", "persistent", "fused_pair"],
+                    choices=["fused", "two_phase", "persistent", "fused_pair", "fused_triple"],
                     help="launch strategy; default: autotuned (mevp_tune) before the timed region")
     ap.add_argument("--tile", default=None, help="owned tile, e.g. 16x14 (with --strategy)")
     ap.add_argument("--no-variants", action="store_true")
@@ -282,7 +283,8 @@ def main():
     if args.record_traffic:
         key, fcsv, wcsv = args.record_traffic
         strategy = key.split("/")[2]
-        kern = {"two_phase": "k_element<", "fused_pair": "k_fused_pair<"}.get(strategy, "k_fused<")
+        kern = {"two_phase": "k_element<", "fused_pair": "k_fused_multi<",
+                "fused_triple": "k_fused_multi<"}.get(strategy, "k_fused<")
         record_traffic(key, fcsv, wcsv, args.copy_mib, kern, args.record_command)
         return
     if args.gpus != 1:
@@ -301,7 +303,8 @@ def main():
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
     if args.traffic_probe:
         strategy = args.strategy or "fused"
-        n_probe = 4 if strategy == "fused_pair" else 3  # whole launches of the kernel only
+        # whole launches of the kernel only
+        n_probe = {"fused_pair": 4, "fused_triple": 6}.get(strategy, 3)
         traffic_probe(args.workload, args.precision, strategy, tile or (16, 14),
                       args.n_sub if args.n_sub != 100 else n_probe, args.copy_mib)
         return
@@ -320,6 +323,7 @@ def main():
                 (args.workload, args.precision, args.steps, "two_phase", None),
                 (args.workload, args.precision, args.steps, "fused", (16, 16)),
                 (args.workload, args.precision, args.steps, "fused_pair", (16, 16)),
+                (args.workload, args.precision, args.steps, "fused_triple", (16, 16)),
                 (args.workload, args.precision, 3, "persistent", (16, 14)),
                 ("1024x1024-dg2", "fp64", 3, None, None), ("1024x1024-dg2", "mixed", 3, None, None),
                 ("2048x2048-dg2", "fp64", 3, None, None), ("2048x2048-dg2", "mixed", 3, None, None),

@@ -110,12 +110,17 @@ typedef struct {
  * blocking): each workgroup recomputes a halo of two elements, keeps the
  * intermediate velocity in LDS and the intermediate stress in registers, so
  * v and S cross HBM once per two subcycles; an odd count ends with one FUSED
- * launch. */
+ * launch.
+ * FUSED_TRIPLE: three subcycles per launch likewise (halo of three elements;
+ * n_a = 1 only); a remainder of one or two subcycles ends the call. If any
+ * domain has general (non-parallelogram) cells it runs two per launch.
+ * All strategies give bitwise-identical results. */
 typedef enum {
   MEVP_STRATEGY_FUSED = 0,
   MEVP_STRATEGY_TWO_PHASE = 1,
   MEVP_STRATEGY_PERSISTENT = 2,
-  MEVP_STRATEGY_FUSED_PAIR = 3
+  MEVP_STRATEGY_FUSED_PAIR = 3,
+  MEVP_STRATEGY_FUSED_TRIPLE = 4
 } mevp_strategy;
 
 /* Launch configuration: strategy and the fused kernels' tile of owned
@@ -150,7 +155,8 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
                         size_t ws_bytes, void *hip_stream, mevp_ctx **out);
 
 /* Select how subcycles are launched (default MEVP_STRATEGY_FUSED, tile
- * 16 x 14). set_config: EINVAL for an unknown strategy or tile; it waits for
+ * 16 x 14). set_config: EINVAL for an unknown strategy or tile, or FUSED_TRIPLE
+ * or a tile other than 16 x 14 with n_a != 1; it waits for
  * the stream when the tile changes. */
 mevp_status mevp_set_strategy(mevp_ctx *ctx, mevp_strategy strategy);
 mevp_status mevp_set_config(mevp_ctx *ctx, const mevp_config *config);

@@ -545,7 +545,7 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
     f.shape = ctx->shape;
     f.persist = 1;
     f.n_sub = n;
-    f.pair = 0;
+    f.depth = 1;
     const int slot = timer_start(ctx, 0);
     hipError_t e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->tile_split,
                                          f, stream);
@@ -560,22 +560,28 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
   for (int it = 0; it < n; ++it) {
     hipError_t e;
     if (ctx->strategy != MEVP_STRATEGY_TWO_PHASE) {
-      // FUSED_PAIR: two subcycles per launch while at least two remain
-      const bool pair = ctx->strategy == MEVP_STRATEGY_FUSED_PAIR && it + 1 < n;
+      // FUSED_PAIR / FUSED_TRIPLE: 2 / 3 subcycles per launch while that many
+      // remain, then the rest in one launch
+      // (three per launch exist for parallelogram cells only: with any general
+      // domain FUSED_TRIPLE runs two per launch)
+      const int most = ctx->strategy == MEVP_STRATEGY_FUSED_TRIPLE
+                           ? (ctx->tile_split.n_gen == 0 ? 3 : 2)
+                       : ctx->strategy == MEVP_STRATEGY_FUSED_PAIR ? 2 : 1;
+      const int depth = most < n - it ? most : n - it;
       const int nxt = ctx->cur ^ 1;
       FusedArgs f;
       f.b0 = Bufs{v_buf(ctx, ctx->cur), v_buf(ctx, nxt), S_buf(ctx, ctx->cur), S_buf(ctx, nxt)};
       f.b1 = f.b0;
       f.shape = ctx->shape;
       f.persist = 0;
-      f.n_sub = pair ? 2 : 1;
-      f.pair = pair ? 1 : 0;
+      f.n_sub = depth;
+      f.depth = depth;
       const int slot = timer_start(ctx, 0);
       e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->tile_split, f,
                                 stream);
       timer_stop(ctx, 0, slot);
       if (e == hipSuccess) ctx->cur = nxt;
-      if (pair) ++it;
+      it += depth - 1;
     } else {
       const Bufs b{v_buf(ctx, ctx->cur), v_buf(ctx, ctx->cur), S_buf(ctx, ctx->cur),
                    S_buf(ctx, ctx->cur)};
@@ -647,12 +653,14 @@ mevp_status mevp_get_config(mevp_ctx *ctx, mevp_config *out) {
 mevp_status mevp_set_config(mevp_ctx *ctx, const mevp_config *cfg) {
   if (!ctx || !cfg) return MEVP_EINVAL;
   if (cfg->strategy != MEVP_STRATEGY_FUSED && cfg->strategy != MEVP_STRATEGY_TWO_PHASE &&
-      cfg->strategy != MEVP_STRATEGY_PERSISTENT && cfg->strategy != MEVP_STRATEGY_FUSED_PAIR)
+      cfg->strategy != MEVP_STRATEGY_PERSISTENT && cfg->strategy != MEVP_STRATEGY_FUSED_PAIR &&
+      cfg->strategy != MEVP_STRATEGY_FUSED_TRIPLE)
     return MEVP_EINVAL;
   int shape = -1;
   for (int sh = 0; sh < kNumTileShapes; ++sh)
     if (kTileShapes[sh][0] - 1 == cfg->tile_nx && kTileShapes[sh][1] - 1 == cfg->tile_ny) shape = sh;
   if (shape < 0 || (shape != 0 && ctx->na != 1)) return MEVP_EINVAL;  // see kTileShapes
+  if (cfg->strategy == MEVP_STRATEGY_FUSED_TRIPLE && ctx->na != 1) return MEVP_EINVAL;
   ctx->strategy = static_cast<mevp_strategy>(cfg->strategy);
   graphs_clear(ctx);
   if (shape != ctx->shape) {
@@ -880,6 +888,9 @@ mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_c
     cand.push_back(mevp_config{MEVP_STRATEGY_FUSED, kTileShapes[sh][0] - 1, kTileShapes[sh][1] - 1});
     cand.push_back(
         mevp_config{MEVP_STRATEGY_FUSED_PAIR, kTileShapes[sh][0] - 1, kTileShapes[sh][1] - 1});
+    if (ctx->na == 1)
+      cand.push_back(
+          mevp_config{MEVP_STRATEGY_FUSED_TRIPLE, kTileShapes[sh][0] - 1, kTileShapes[sh][1] - 1});
   }
   cand.push_back(mevp_config{MEVP_STRATEGY_TWO_PHASE, kTileShapes[0][0] - 1, kTileShapes[0][1] - 1});
   cand.push_back(mevp_config{MEVP_STRATEGY_PERSISTENT, kTileShapes[0][0] - 1, kTileShapes[0][1] - 1});

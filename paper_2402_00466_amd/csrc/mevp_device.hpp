@@ -246,6 +246,50 @@ struct DomBufs {
 };
 
 // ---------------------------------------------------------------------------
+// A DG function sum_k c[k] psi_k at the Gauss points, by sum factorisation
+// over the tensor-product basis psi_k = P_kx(xi) P_ky(eta):
+//   w[ky][i] = sum_{k: kDgY[k] = ky} c[k] P_kDgX[k](x_i),
+//   at(i, j) = sum_ky w[ky][i] P_ky(x_j),
+// with the zero factors (P_1 at the centre point) skipped at compile time
+// (every index is a constant after unrolling).
+// ---------------------------------------------------------------------------
+template <int NS, int NGP, class T>
+struct DgGauss {
+  T w[3][NGP];
+  bool hw[3][NGP];
+  __device__ __forceinline__ explicit DgGauss(const T (&c)[NS]) {
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int i = 0; i < NGP; ++i) {
+        T acc = T(0);
+        bool have = false;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          const double f = dg_1d(kDgX[k], Gauss1D<NGP>::x[i]);
+          if (kDgY[k] != ky || f == 0.0) continue;
+          acc = have ? acc + c[k] * T(f) : c[k] * T(f);
+          have = true;
+        }
+        w[ky][i] = acc;
+        hw[ky][i] = have;
+      }
+  }
+  __device__ __forceinline__ T at(int i, int j) const {
+    T acc = T(0);
+    bool have = false;
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      const double f = dg_1d(ky, Gauss1D<NGP>::x[j]);
+      if (!hw[ky][i] || f == 0.0) continue;
+      acc = have ? acc + w[ky][i] * T(f) : w[ky][i] * T(f);
+      have = true;
+    }
+    return acc;
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Geometry of one element as the element update needs it: the constant
 // Jacobian of a parallelogram cell, or the bilinear map of a general cell.
 // ---------------------------------------------------------------------------
@@ -326,20 +370,13 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, tr
 
   // ---- stress update ----
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
+  const DgGauss<NS, Ngp<NS>::value, T> g11(E11), g12(E12), g22(E22);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
-    T e11 = 0, e12 = 0, e22 = 0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      if (Q::psi(k, q) != 0.0) {
-        const T ps = T(Q::psi(k, q));
-        e11 += E11[k] * ps;
-        e12 += E12[k] * ps;
-        e22 += E22[k] * ps;
-      }
-    }
+    const int i = q % Ngp<NS>::value, j = q / Ngp<NS>::value;
+    const T e11 = g11.at(i, j), e12 = g12.at(i, j), e22 = g22.at(i, j);
     const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
     T s11, s12, s22;
     vp_stress<T>(p, P, e11, e12, e22, s11, s12, s22);
@@ -355,27 +392,34 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, tr
   }
   relax<NS, T>(p, sold, R11, R12, R22);
 
-  // ---- divergence, element part ----
+  // ---- divergence, element part: the adjugate-weighted stress per
+  // coefficient first, then the transposed reference operators ----
+  T Gxx[NS], Gxe[NS], Gyx[NS], Gye[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    Gxx[k] = J11 * R11[k] - J01 * R12[k];
+    Gxe[k] = J00 * R12[k] - J10 * R11[k];
+    Gyx[k] = J11 * R12[k] - J01 * R22[k];
+    Gye[k] = J00 * R22[k] - J10 * R12[k];
+  }
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
-    T bx11 = 0, be11 = 0, bx12 = 0, be12 = 0, bx22 = 0, be22 = 0;
+    T bx = 0, by = 0;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (a_xi(k, a) != 0.0) {
         const T c = T(a_xi(k, a));
-        bx11 += c * R11[k];
-        bx12 += c * R12[k];
-        bx22 += c * R22[k];
+        bx += c * Gxx[k];
+        by += c * Gyx[k];
       }
       if (a_eta(k, a) != 0.0) {
         const T c = T(a_eta(k, a));
-        be11 += c * R11[k];
-        be12 += c * R12[k];
-        be22 += c * R22[k];
+        bx += c * Gxe[k];
+        by += c * Gye[k];
       }
     }
-    fx[a] = -((J11 * bx11 - J01 * bx12) + (J00 * be12 - J10 * be11));
-    fy[a] = -((J11 * bx12 - J01 * bx22) + (J00 * be22 - J10 * be12));
+    fx[a] = -bx;
+    fy[a] = -by;
   }
 }
 
@@ -437,20 +481,13 @@ __device__ __forceinline__ void element_general(const KParams &p, const Geo<T, f
 
   // ---- stress update ----
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
+  const DgGauss<NS, Ngp<NS>::value, T> g11(E11), g12(E12), g22(E22);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
-    T e11 = 0, e12 = 0, e22 = 0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      if (Q::psi(k, q) != 0.0) {
-        const T ps = T(Q::psi(k, q));
-        e11 += E11[k] * ps;
-        e12 += E12[k] * ps;
-        e22 += E22[k] * ps;
-      }
-    }
+    const int i = q % Ngp<NS>::value, j = q / Ngp<NS>::value;
+    const T e11 = g11.at(i, j), e12 = g12.at(i, j), e22 = g22.at(i, j);
     const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
     T s11, s12, s22;
     vp_stress<T>(p, P, e11, e12, e22, s11, s12, s22);
@@ -476,18 +513,11 @@ __device__ __forceinline__ void element_general(const KParams &p, const Geo<T, f
   //      = -sum_q (dphi_a/dxi Gxi + dphi_a/deta Geta) with G = w_q sigma adj(J)^T ----
 #pragma unroll
   for (int a = 0; a < 9; ++a) fx[a] = fy[a] = T(0);
+  const DgGauss<NS, Ngp<NS>::value, T> r11(R11), r12(R12), r22(R22);
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
-    T s11 = 0, s12 = 0, s22 = 0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      if (Q::psi(k, q) != 0.0) {
-        const T ps = T(Q::psi(k, q));
-        s11 += R11[k] * ps;
-        s12 += R12[k] * ps;
-        s22 += R22[k] * ps;
-      }
-    }
+    const int i = q % Ngp<NS>::value, j = q / Ngp<NS>::value;
+    const T s11 = r11.at(i, j), s12 = r12.at(i, j), s22 = r22.at(i, j);
     T J00, J01, J10, J11;
     cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
     const T w = T(Q::w(q));
@@ -665,6 +695,11 @@ __device__ __forceinline__ void update_nodes(const KParams &p, const DomDev &D, 
   const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
   const size_t nn = (size_t)D.nn;
   const int w = ix1 - ix0, n = w * (iy1 - iy0);
+  // k / w via a float reciprocal: for k < 2^13 and w < 2^7 the product
+  // (k + 1/2) (1/w) is within 1e-3 of (k + 1/2) / w, which lies at least
+  // 1/(2w) from an integer, so the truncation is exact
+  static_assert(R * NT <= 8192, "node rounds beyond the exact float division");
+  const float rw = 1.0f / (float)w;
   int jn[R], ixs[R], iys[R];
   bool act[R], bnd[R];
   double ux[R], uy[R], o[R][6];
@@ -672,8 +707,9 @@ __device__ __forceinline__ void update_nodes(const KParams &p, const DomDev &D, 
   for (int m = 0; m < R; ++m) {
     const int k = tid + m * NT;
     act[m] = k < n;
-    ixs[m] = ix0 + (act[m] ? k % w : 0);
-    iys[m] = iy0 + (act[m] ? k / w : 0);
+    const int qy = act[m] ? (int)(((float)k + 0.5f) * rw) : 0;
+    ixs[m] = ix0 + (act[m] ? k - qy * w : 0);
+    iys[m] = iy0 + qy;
     jn[m] = iys[m] * NX + ixs[m];
     bnd[m] = ixs[m] == 0 || iys[m] == 0 || ixs[m] == NX - 1 || iys[m] == NY - 1;
     if (act[m] && !bnd[m]) {
@@ -765,27 +801,29 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
 }
 
 // ---------------------------------------------------------------------------
-// Two subcycles on one tile in one pass (temporal blocking). The tile of
-// owned (EX-1) x (EY-1) elements (the same tiles as fused_tile) takes a halo
-// of two elements on its low sides and one on its high sides:
-//   A  elements [x0-2, x0+TX] x [y0-2, y0+TY] (one per lane): element update
-//      from v^{p-1}, S^{p-1} in global memory; forces to LDS, the new stress
-//      kept in registers;
-//   B  nodes [2x0-2, 2x0+2TX] x [...]: velocity update to v^p, kept in LDS;
-//   C  elements [x0-1, x0+TX-1] x [...] (the same lanes): element update from
-//      v^p in LDS and S^p in registers; S^{p+1} of the owned elements stored;
-//   D  the owned nodes: velocity update from v^p in LDS to v^{p+1}, stored.
-// Every element and node update is the same arithmetic as in fused_tile, so
-// two passes of this kernel equal four single subcycles bit for bit. Only
-// v^{p-1} / S^{p-1} are read and only v^{p+1} / S^{p+1} written (double
-// buffering as in fused_tile).
+// K subcycles on one tile in one pass (temporal blocking, K = 2 or 3). The
+// tile of owned (EX-1) x (EY-1) elements (the same tiles as fused_tile) takes
+// a halo of K elements on its low sides and K-1 on its high sides; lane
+// (lx, ly) holds element (x0-K+lx, y0-K+ly) for the whole pass. Subcycle i:
+//   element phase  elements [x0-K+i, x0+TX+K-2-i] (likewise in y): element
+//                  update from v in global memory (i = 0) or LDS, and S in
+//                  global memory (i = 0) or in the lane's registers; forces
+//                  to LDS, the new stress kept in registers (the owned
+//                  elements' stress stored at i = K-1);
+//   node phase     i < K-1: the nodes of the next element phase, velocity
+//                  update in place in LDS; i = K-1: the owned nodes, stored.
+// Every element and node update is the arithmetic of fused_tile, so a pass
+// equals K single subcycles bit for bit. Only v^{p-1} / S^{p-1} are read
+// and only v^{p+K-1} / S^{p+K-1} written (double buffering as in fused_tile).
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class TS, bool AFF, int EX, int EY>
-__global__ void __launch_bounds__((EX + 2) * (EY + 2))
-    k_fused_pair(DevArrays d, KParams p, const Tile *tiles, Bufs b) {
+template <int NS, int NA, class T, class TS, bool AFF, int EX, int EY, int K>
+__global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
+    k_fused_multi(DevArrays d, KParams p, const Tile *tiles, Bufs b) {
+  static_assert(K == 2 || K == 3, "two or three subcycles per pass");
   constexpr int TX = EX - 1, TY = EY - 1;
-  constexpr int FX = EX + 2, FY = EY + 2, NT = FX * FY;  // phase A elements = lanes
-  constexpr int VW = 2 * EX + 1, VH = 2 * EY + 1;         // phase B nodes
+  constexpr int FX = EX + 2 * K - 2, FY = EY + 2 * K - 2, NT = FX * FY;  // lanes = elements
+  // nodes of element phase 1, in LDS: [2 (x0-K+1), 2 (x0+TX+K-2)]
+  constexpr int VW = 2 * TX + 4 * K - 5, VH = 2 * TY + 4 * K - 5;
   __shared__ T fl[18][NT];
   __shared__ double vl[2][VW * VH];
   const Tile t = tiles[blockIdx.x];
@@ -795,89 +833,95 @@ __global__ void __launch_bounds__((EX + 2) * (EY + 2))
   const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
   const size_t nn = (size_t)D.nn, ne = (size_t)D.ne;
   const double *nc = d.nc + (size_t)6 * D.node_off;
+  const int ex0 = t.x0 - K, ey0 = t.y0 - K;  // element of lane (0, 0)
+  const int jx0 = 2 * (ex0 + 1), jy0 = 2 * (ey0 + 1);  // node of LDS entry (0, 0)
   const int lx = tid % FX, ly = tid / FX;
-  const int ex = t.x0 - 2 + lx, ey = t.y0 - 2 + ly;
-  const bool in1 = ex >= 0 && ey >= 0 && ex < D.nx && ey < D.ny;
-  const int el = in1 ? ey * D.nx + ex : 0;
+  const int ex = ex0 + lx, ey = ey0 + ly;
+  const bool exists = ex >= 0 && ey >= 0 && ex < D.nx && ey < D.ny;
+  const int el = exists ? ey * D.nx + ex : 0;
 
-  // ---- A ----
   Geo<T, AFF> g{};
   double Hc[NA], Ac[NA];
-  T S11[NS], S12[NS], S22[NS];  // S^p, as stored (rounded to TS)
-  if (in1) {
-    g = load_geo<T, AFF>(d, D, ex, ey);
-    T vx[9], vy[9];
-    load_velocity<T>(D, B.v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
-    load_ice<NA>(d, D, el, Hc, Ac);
-    auto sold = [&](int c, int k) { return T(B.S_in[(c * NS + k) * ne + el]); };
-    T fx[9], fy[9];
-    element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, S11, S12, S22, fx, fy);
+  T S11[NS], S12[NS], S22[NS];  // the lane's stress, as stored (rounded to TS)
+  auto vlds = [&](int ix, int iy) { return (iy - jy0) * VW + (ix - jx0); };
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      S11[k] = T(TS(S11[k]));
-      S12[k] = T(TS(S12[k]));
-      S22[k] = T(TS(S22[k]));
-    }
+  for (int i = 0; i < K; ++i) {
+    // ---- element phase i ----
+    if (exists && lx >= i && ly >= i && lx < FX - i && ly < FY - i) {
+      T vx[9], vy[9];
+      T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
+      if (i == 0) {
+        g = load_geo<T, AFF>(d, D, ex, ey);
+        load_ice<NA>(d, D, el, Hc, Ac);
+        load_velocity<T>(D, B.v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
+        auto sold = [&](int c, int k) { return T(B.S_in[(c * NS + k) * ne + el]); };
+        element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+      } else {
+        gather_velocity<T>(vl[0], vl[1], vlds(2 * ex, 2 * ey), VW, vx, vy);
+        auto sold = [&](int c, int k) { return c == 0 ? S11[k] : c == 1 ? S12[k] : S22[k]; };
+        element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+      }
+      if (i == K - 1) {
+        if (lx >= K && ly >= K) store_stress<NS, T, TS>(B.S_out, ne, el, R11, R12, R22);
+      } else {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-      fl[a][tid] = fx[a];
-      fl[9 + a][tid] = fy[a];
-    }
-  }
-  __syncthreads();
-
-  // ---- B: v^p on the nodes of the phase C elements, into LDS ----
-  {
-    const int jx0 = 2 * t.x0 - 2, jy0 = 2 * t.y0 - 2;  // LDS origin
-    const int ix0 = max(jx0, 0), iy0 = max(jy0, 0);
-    const int ix1 = min(jx0 + VW, NX), iy1 = min(jy0 + VH, NY);
-    constexpr int R = (VW * VH + NT - 1) / NT;
-    auto uin = [&](int, int, int j, double &ux, double &uy) {
-      ux = B.v_in[j];
-      uy = B.v_in[nn + j];
-    };
-    auto out = [&](int ix, int iy, int, double vx, double vy) {
-      const int q = (iy - jy0) * VW + (ix - jx0);
-      vl[0][q] = vx;
-      vl[1][q] = vy;
-    };
-    update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, t.x0 - 2, t.y0 - 2, fl, uin, out);
-  }
-  __syncthreads();
-
-  // ---- C ----
-  if (in1 && lx >= 1 && ly >= 1 && lx <= EX && ly <= EY) {
-    T vx[9], vy[9];
-    gather_velocity<T>(vl[0], vl[1], (2 * ly - 2) * VW + 2 * lx - 2, VW, vx, vy);
-    auto sold = [&](int c, int k) { return c == 0 ? S11[k] : c == 1 ? S12[k] : S22[k]; };
-    T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
-    element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
-    if (lx >= 2 && ly >= 2) store_stress<NS, T, TS>(B.S_out, ne, el, R11, R12, R22);
+        for (int k = 0; k < NS; ++k) {
+          S11[k] = T(TS(R11[k]));
+          S12[k] = T(TS(R12[k]));
+          S22[k] = T(TS(R22[k]));
+        }
+      }
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-      fl[a][tid] = fx[a];
-      fl[9 + a][tid] = fy[a];
+      for (int a = 0; a < 9; ++a) {
+        fl[a][tid] = fx[a];
+        fl[9 + a][tid] = fy[a];
+      }
     }
-  }
-  __syncthreads();
-
-  // ---- D: the owned nodes, v^{p+1} to global memory ----
-  {
-    const int jx0 = 2 * t.x0 - 2, jy0 = 2 * t.y0 - 2;
-    const int ix0 = 2 * t.x0, iy0 = 2 * t.y0;
-    const int ix1 = (t.x0 + TX >= D.nx) ? NX : ix0 + 2 * TX;
-    const int iy1 = (t.y0 + TY >= D.ny) ? NY : iy0 + 2 * TY;
-    constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;
-    auto uin = [&](int ix, int iy, int, double &ux, double &uy) {
-      const int q = (iy - jy0) * VW + (ix - jx0);
-      ux = vl[0][q];
-      uy = vl[1][q];
-    };
-    auto out = [&](int, int, int j, double vx, double vy) {
-      B.v_out[j] = vx;
-      B.v_out[nn + j] = vy;
-    };
-    update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, t.x0 - 2, t.y0 - 2, fl, uin, out);
+    __syncthreads();
+    // ---- node phase i ----
+    if (i < K - 1) {
+      // nodes of element phase i+1: [2 (x0-K+i+1), 2 (x0+TX+K-2-i)]
+      const int ix0 = max(2 * (ex0 + i + 1), 0), iy0 = max(2 * (ey0 + i + 1), 0);
+      const int ix1 = min(2 * (t.x0 + TX + K - 2 - i) + 1, NX);
+      const int iy1 = min(2 * (t.y0 + TY + K - 2 - i) + 1, NY);
+      constexpr int R = (VW * VH + NT - 1) / NT;
+      auto out = [&](int ix, int iy, int, double vx, double vy) {
+        const int q = vlds(ix, iy);
+        vl[0][q] = vx;
+        vl[1][q] = vy;
+      };
+      if (i == 0) {
+        auto uin = [&](int, int, int j, double &ux, double &uy) {
+          ux = B.v_in[j];
+          uy = B.v_in[nn + j];
+        };
+        update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, ex0, ey0, fl, uin, out);
+      } else {
+        auto uin = [&](int ix, int iy, int, double &ux, double &uy) {
+          const int q = vlds(ix, iy);
+          ux = vl[0][q];
+          uy = vl[1][q];
+        };
+        update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, ex0, ey0, fl, uin, out);
+      }
+    } else {
+      // the owned nodes, v to global memory
+      const int ix0 = 2 * t.x0, iy0 = 2 * t.y0;
+      const int ix1 = (t.x0 + TX >= D.nx) ? NX : ix0 + 2 * TX;
+      const int iy1 = (t.y0 + TY >= D.ny) ? NY : iy0 + 2 * TY;
+      constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;
+      auto uin = [&](int ix, int iy, int, double &ux, double &uy) {
+        const int q = vlds(ix, iy);
+        ux = vl[0][q];
+        uy = vl[1][q];
+      };
+      auto out = [&](int, int, int j, double vx, double vy) {
+        B.v_out[j] = vx;
+        B.v_out[nn + j] = vy;
+      };
+      update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, ex0, ey0, fl, uin, out);
+    }
+    if (i < K - 1) __syncthreads();
   }
 }
 
@@ -1212,15 +1256,25 @@ inline hipError_t two_phase_t(const DevArrays &d, const KParams &p, const Launch
   return hipGetLastError();
 }
 
-// Fused subcycle(s): tile kernel(s), parallelogram tiles first; f.pair: the
-// two-subcycle kernel.
+// Fused subcycle(s): tile kernel(s), parallelogram tiles first; f.depth 2 or 3:
+// the kernel that runs that many subcycles per pass.
 template <int NS, int NA, class T, bool AFF, int EX, int EY>
 inline hipError_t fused_one(const DevArrays &d, const KParams &p, const Tile *tiles, int ntiles,
                             const FusedArgs &f, hipStream_t s) {
-  if (f.pair) {
-    hipLaunchKernelGGL((k_fused_pair<NS, NA, T, T, AFF, EX, EY>), dim3(ntiles),
+  if (f.depth == 2) {
+    hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, AFF, EX, EY, 2>), dim3(ntiles),
                        dim3((EX + 2) * (EY + 2)), 0, s, d, p, tiles, f.b0);
     return hipGetLastError();
+  }
+  if (f.depth == 3) {
+    // three subcycles per pass: built for parallelogram cells and one ice dof
+    // only (the general-cell update would spill at this occupancy)
+    if constexpr (NA == 1 && AFF) {
+      hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, AFF, EX, EY, 3>), dim3(ntiles),
+                         dim3((EX + 4) * (EY + 4)), 0, s, d, p, tiles, f.b0);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
   }
   auto kern = k_fused<NS, NA, T, T, AFF, EX, EY>;
   if (!f.persist) {

@@ -46,7 +46,7 @@ struct FusedArgs {
   int shape;       // index into kTileShapes
   int persist;     // 1: one cooperative launch for n_sub subcycles
   int n_sub;
-  int pair;        // 1: two subcycles in one launch (k_fused_pair, buffers b0)
+  int depth;       // subcycles per launch of k_fused_multi (2, 3; buffers b0), else 1
 };
 
 // Leading blocks (or tiles) of parallelogram-cell domains, then the rest.

@@ -112,6 +112,11 @@ constexpr double kNorm1D[3] = {1.0, 1.0 / 12.0, 1.0 / 180.0};
 constexpr int kDgX[8] = {0, 1, 0, 2, 1, 0, 2, 1};
 constexpr int kDgY[8] = {0, 0, 1, 0, 1, 2, 1, 2};
 
+// 1D factors of the DG basis: psi_k(xi, eta) = dg_1d(kDgX[k], xi) dg_1d(kDgY[k], eta)
+constexpr double dg_1d(int i, double x) {
+  return i == 0 ? 1.0 : (i == 1 ? x - 0.5 : (x - 0.5) * (x - 0.5) - 1.0 / 12.0);
+}
+
 // Axi[k][a] = int psi_k dphi_a/dxi, Aeta[k][a] = int psi_k dphi_a/deta over the
 // reference square (local node a = 3 b + c).
 constexpr double a_xi(int k, int a) { return kI1[kDgX[k]][a % 3] * kI0[kDgY[k]][a / 3]; }

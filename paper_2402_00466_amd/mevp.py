@@ -17,7 +17,8 @@ from . import build as _build
 
 FP64 = 0
 MIXED = 1
-STRATEGIES = {"fused": 0, "two_phase": 1, "persistent": 2, "fused_pair": 3}
+STRATEGIES = {"fused": 0, "two_phase": 1, "persistent": 2, "fused_pair": 3,
+              "fused_triple": 4}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 TILES = [(16, 14), (16, 16), (32, 14)]
 _PREC = {"fp64": FP64, "f64": FP64, "mixed": MIXED}

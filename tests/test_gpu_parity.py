@@ -55,10 +55,13 @@ WHOLE_RUNS = [
 ]
 
 
-@pytest.mark.parametrize("strategy", ["fused", "two_phase", "persistent", "fused_pair"])
+@pytest.mark.parametrize("strategy", ["fused", "two_phase", "persistent", "fused_pair",
+                                      "fused_triple"])
 @pytest.mark.parametrize("case", WHOLE_RUNS, ids=lambda c: "x".join(map(str, c[:4])))
 def test_whole_run_fp64(case, strategy):
     nx, ny, ns, na, h, pert, ho, steps, nsub = case
+    if strategy == "fused_triple" and na != 1:
+        pytest.skip("FUSED_TRIPLE exists for n_a = 1 only (its EINVAL is tested below)")
     d = make_domain(nx, ny, ns, na, seed=nx * 100 + ny, h=h, perturb=pert, ho_amp=ho)
     if nx == 1 and ny == 1:
         # the gyre and the current vanish at the single interior node: drive it with a
@@ -195,7 +198,8 @@ def test_equation_relaxation_form():
 
 CONFIGS = [("two_phase", None), ("fused", (16, 16)), ("fused", (32, 14)),
            ("persistent", (16, 14)), ("persistent", (16, 16)), ("persistent", (32, 14)),
-           ("fused_pair", (16, 14)), ("fused_pair", (16, 16)), ("fused_pair", (32, 14))]
+           ("fused_pair", (16, 14)), ("fused_pair", (16, 16)), ("fused_pair", (32, 14)),
+           ("fused_triple", (16, 14)), ("fused_triple", (16, 16)), ("fused_triple", (32, 14))]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -222,21 +226,23 @@ PAIR_FULL = [("256x256-dg2", "fp64"), ("256x256-dg2", "mixed"), ("2048x2048-dg2"
 
 
 @pytest.mark.parametrize("name,precision", PAIR_FULL)
-def test_pair_kernel_bitwise_at_full_size(name, precision):
-    """Two subcycles per launch (every tile shape) against one per launch, at the
-    benchmark sizes, from a seeded state: 5 subcycles (two pair launches and a
-    single one) agree bit for bit; the single-subcycle kernel is itself checked
-    against the oracle at these sizes (test_few_subcycles_full_size_*)."""
+def test_multi_subcycle_kernels_bitwise_at_full_size(name, precision):
+    """Two and three subcycles per launch (every tile shape) against one per
+    launch, at the benchmark sizes, from a seeded state: 5 subcycles (launches
+    of 2 + 2 + 1, or 3 + 2) agree bit for bit; the single-subcycle kernel is
+    itself checked against the oracle at these sizes
+    (test_few_subcycles_full_size_*)."""
     doms = named_workload(name)
     states = [random_state(d.nx, d.ny, d.n_s, seed=99 + k) for k, d in enumerate(doms)]
     ref = gpu_run(doms, 1, 5, precision=precision, states=states)
     tiles = [(16, 14)] + ([(16, 16), (32, 14)] if doms[0].n_a == 1 else [])
-    for tile in tiles:
-        log(f"workload {name} {precision}: fused_pair {tile} vs fused (16, 14), 5 subcycles")
-        got = gpu_run(doms, 1, 5, precision=precision, states=states, strategy="fused_pair",
-                      tile=tile)
-        for k, ((v, S), (vr, Sr)) in enumerate(zip(got, ref)):
-            assert np.array_equal(v, vr) and np.array_equal(S, Sr), (tile, k)
+    for strategy in ("fused_pair", "fused_triple"):
+        for tile in tiles:
+            log(f"workload {name} {precision}: {strategy} {tile} vs fused (16, 14), 5 subcycles")
+            got = gpu_run(doms, 1, 5, precision=precision, states=states, strategy=strategy,
+                          tile=tile)
+            for k, ((v, S), (vr, Sr)) in enumerate(zip(got, ref)):
+                assert np.array_equal(v, vr) and np.array_equal(S, Sr), (strategy, tile, k)
 
 
 def test_persistent_falls_back_for_mixed_cell_kinds():
@@ -257,5 +263,7 @@ def test_tile_shapes_need_one_ice_dof():
         ctx.set_config("fused", (16, 16))
     with pytest.raises(M.MevpError):
         ctx.set_config("fused", (15, 15))
+    with pytest.raises(M.MevpError):
+        ctx.set_config("fused_triple", (16, 14))
     ctx.set_config("persistent", (16, 14))
     assert ctx.get_config() == ("persistent", (16, 14))

@@ -32,7 +32,7 @@ def _state(ctx):
     return v.cpu().numpy(), S.cpu().numpy()
 
 
-@pytest.mark.parametrize("strategy", ["fused", "fused_pair"])
+@pytest.mark.parametrize("strategy", ["fused", "fused_pair", "fused_triple"])
 @pytest.mark.parametrize("n_sub", [10, 7])
 def test_graph_replays_match_eager(M, n_sub, strategy):
     """Graph replay of mevp_step (even and odd n_sub: one or two captured graphs),

@@ -55,6 +55,7 @@ def _floor(d, ref, cache, eps):
 @pytest.mark.parametrize("precision,strategy,tile,eps", [
     ("fp64", "fused", (16, 14), 1e-15),
     ("fp64", "fused_pair", (16, 16), 1e-15),
+    ("fp64", "fused_triple", (16, 16), 1e-15),
     ("mixed", "fused_pair", (16, 16), 1e-7),
 ])
 def test_whole_step_256_within_oracle_noise_floor(setup, precision, strategy, tile, eps):
