@@ -27,6 +27,8 @@ def lib():
         dp = C.POINTER(C.c_double)
         L.or_mesh_create.restype = C.c_void_p
         L.or_mesh_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp]
+        L.or_mesh_create_iso.restype = C.c_void_p
+        L.or_mesh_create_iso.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp]
         L.or_mesh_destroy.argtypes = [C.c_void_p]
         L.or_tables.restype = C.c_int
         L.or_tables.argtypes = [C.c_int, C.c_int] + [dp] * 7
@@ -90,14 +92,24 @@ def _f64(a):
 
 
 class Mesh:
-    """Oracle mesh: nx x ny quads, DG stress with ns dofs, DG ice fields with na dofs."""
+    """Oracle mesh: nx x ny quads, DG stress with ns dofs, DG ice fields with na dofs.
+    Geometry from the cell vertices [2][(nx+1)(ny+1)] (bilinear map) or, with
+    ``nodes`` [2][(2nx+1)(2ny+1)], from the CG2 node positions (isoparametric map)."""
 
-    def __init__(self, nx, ny, ns, na, vertices):
+    def __init__(self, nx, ny, ns, na, vertices=None, nodes=None):
         self.nx, self.ny, self.ns, self.na = nx, ny, ns, na
-        self.vertices = _f64(vertices)
-        if self.vertices.shape != (2, (nx + 1) * (ny + 1)):
-            raise ValueError("vertices must be [2][(nx+1)(ny+1)]")
-        self._h = lib().or_mesh_create(nx, ny, ns, na, _p(self.vertices))
+        if (vertices is None) == (nodes is None):
+            raise ValueError("give exactly one of vertices and nodes")
+        if nodes is not None:
+            self.nodes = _f64(nodes)
+            if self.nodes.shape != (2, (2 * nx + 1) * (2 * ny + 1)):
+                raise ValueError("nodes must be [2][(2nx+1)(2ny+1)]")
+            self._h = lib().or_mesh_create_iso(nx, ny, ns, na, _p(self.nodes))
+        else:
+            self.vertices = _f64(vertices)
+            if self.vertices.shape != (2, (nx + 1) * (ny + 1)):
+                raise ValueError("vertices must be [2][(nx+1)(ny+1)]")
+            self._h = lib().or_mesh_create(nx, ny, ns, na, _p(self.vertices))
         if not self._h:
             raise ValueError("oracle rejected the mesh (sizes, ns/na or a non-positive Jacobian)")
         self.ng = 4 if ns == 3 else 9

@@ -24,6 +24,9 @@
  *     local node a = 3 b + c (c along xi, b along eta).
  *  R8 geometry: bilinear map of the 4 element vertices (the "on-the-fly map"
  *     of Sec. 3.2, four vertices with two values each); planar coordinates.
+ *     Isoparametric variant (Sec. 2.1: the cell map in the velocity's finite
+ *     element space): x(xi, eta) = sum_a X_a phi_a(xi, eta) over the 9 CG2
+ *     nodes of the cell, so cell edges may be curved (quadratic).
  *  R9 strain: eps11 = dvx/dx, eps22 = dvy/dy, eps12 = (dvx/dy + dvy/dx)/2 at
  *     the Gauss points, L2-projected onto the DG stress space (same projection
  *     M^-1 Psi W as the stress update's iMJwPSI).
@@ -75,6 +78,8 @@ struct or_mesh {
   double *dphiy; /* [ne][9][ng] */
   double *chol;  /* [ne][ns][ns], lower triangle */
   double *vx, *vy; /* copy of the vertices [(nx+1)(ny+1)] */
+  int iso;         /* 1: isoparametric CG2 map from the node coordinates below */
+  double *nx_, *ny_; /* CG2 node coordinates [(2nx+1)(2ny+1)] (iso only) */
 };
 
 int or_num_threads(void) {
@@ -219,8 +224,40 @@ static void chol_solve(int n, const double *L, double *x) {
   }
 }
 
-or_mesh *or_mesh_create(int nx, int ny, int ns, int na, const double *vertices) {
-  if (nx < 1 || ny < 1 || !vertices) return NULL;
+/* J = d(x, y)/d(xi, eta) of element e at (xi, eta): J[0] = dx/dxi,
+ * J[1] = dx/deta, J[2] = dy/dxi, J[3] = dy/deta. Bilinear map of the 4
+ * vertices (R8), or the isoparametric map of the 9 CG2 nodes. */
+static void map_jacobian(const or_mesh *m, int e, double xi, double eta, double *J) {
+  int ex = e % m->nx, ey = e / m->nx;
+  if (!m->iso) {
+    int vi[4] = {vert_index(m, ex, ey), vert_index(m, ex + 1, ey), vert_index(m, ex, ey + 1),
+                 vert_index(m, ex + 1, ey + 1)};
+    double X[4], Y[4];
+    for (int i = 0; i < 4; ++i) {
+      X[i] = m->vx[vi[i]];
+      Y[i] = m->vy[vi[i]];
+    }
+    J[0] = (1.0 - eta) * (X[1] - X[0]) + eta * (X[3] - X[2]);
+    J[1] = (1.0 - xi) * (X[2] - X[0]) + xi * (X[3] - X[1]);
+    J[2] = (1.0 - eta) * (Y[1] - Y[0]) + eta * (Y[3] - Y[2]);
+    J[3] = (1.0 - xi) * (Y[2] - Y[0]) + xi * (Y[3] - Y[1]);
+    return;
+  }
+  J[0] = J[1] = J[2] = J[3] = 0.0;
+  for (int a = 0; a < 9; ++a) {
+    int j = local_to_global(m, e, a);
+    double dx = dlag2(a % 3, xi) * lag2(a / 3, eta);
+    double dy = lag2(a % 3, xi) * dlag2(a / 3, eta);
+    J[0] += m->nx_[j] * dx;
+    J[1] += m->nx_[j] * dy;
+    J[2] += m->ny_[j] * dx;
+    J[3] += m->ny_[j] * dy;
+  }
+}
+
+/* Mesh record with the reference tables, without geometry. */
+static or_mesh *mesh_alloc(int nx, int ny, int ns, int na) {
+  if (nx < 1 || ny < 1) return NULL;
   if (ngp_for(ns) < 0 || !(na == 1 || na == 3 || na == 6)) return NULL;
   or_mesh *m = (or_mesh *)calloc(1, sizeof(or_mesh));
   if (!m) return NULL;
@@ -250,30 +287,23 @@ or_mesh *or_mesh_create(int nx, int ny, int ns, int na, const double *vertices) 
     or_mesh_destroy(m);
     return NULL;
   }
-  const double *VX = vertices, *VY = vertices + (size_t)(nx + 1) * (ny + 1);
-  memcpy(m->vx, VX, sizeof(double) * nv);
-  memcpy(m->vy, VY, sizeof(double) * nv);
+  return m;
+}
+
+/* Per-element geometry at the Gauss points and the Cholesky factor of M_e;
+ * -1 if some Jacobian determinant is not positive. */
+static int mesh_geometry(or_mesh *m) {
+  size_t ne = (size_t)m->nx * m->ny, ng = m->ng;
+  int ns = m->ns;
   int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
   for (long e = 0; e < (long)ne; ++e) {
-    int ex = (int)(e % nx), ey = (int)(e / nx);
-    /* vertices in the order (0,0), (1,0), (0,1), (1,1) of the reference square */
-    int vi[4] = {vert_index(m, ex, ey), vert_index(m, ex + 1, ey), vert_index(m, ex, ey + 1),
-                 vert_index(m, ex + 1, ey + 1)};
-    double X[4], Y[4];
-    for (int i = 0; i < 4; ++i) {
-      X[i] = VX[vi[i]];
-      Y[i] = VY[vi[i]];
-    }
     double *wd = m->wdet + e * ng, *gx = m->dphix + e * 9 * ng, *gy = m->dphiy + e * 9 * ng;
     for (int q = 0; q < m->ng; ++q) {
-      double xi, eta, w;
+      double xi, eta, w, J[4];
       gauss_point(m, q, &xi, &eta, &w);
-      /* J = d(x,y)/d(xi,eta) of the bilinear map */
-      double J00 = (1.0 - eta) * (X[1] - X[0]) + eta * (X[3] - X[2]);
-      double J01 = (1.0 - xi) * (X[2] - X[0]) + xi * (X[3] - X[1]);
-      double J10 = (1.0 - eta) * (Y[1] - Y[0]) + eta * (Y[3] - Y[2]);
-      double J11 = (1.0 - xi) * (Y[2] - Y[0]) + xi * (Y[3] - Y[1]);
+      map_jacobian(m, (int)e, xi, eta, J);
+      double J00 = J[0], J01 = J[1], J10 = J[2], J11 = J[3];
       double det = J00 * J11 - J01 * J10;
       if (!(det > 0.0)) bad = 1;
       wd[q] = w * det;
@@ -295,7 +325,44 @@ or_mesh *or_mesh_create(int nx, int ny, int ns, int na, const double *vertices) 
       }
     if (cholesky(ns, M, m->chol + e * ns * ns) != 0) bad = 1;
   }
-  if (bad) {
+  return bad ? -1 : 0;
+}
+
+or_mesh *or_mesh_create(int nx, int ny, int ns, int na, const double *vertices) {
+  if (!vertices) return NULL;
+  or_mesh *m = mesh_alloc(nx, ny, ns, na);
+  if (!m) return NULL;
+  size_t nv = (size_t)(nx + 1) * (ny + 1);
+  memcpy(m->vx, vertices, sizeof(double) * nv);
+  memcpy(m->vy, vertices + nv, sizeof(double) * nv);
+  if (mesh_geometry(m) != 0) {
+    or_mesh_destroy(m);
+    return NULL;
+  }
+  return m;
+}
+
+or_mesh *or_mesh_create_iso(int nx, int ny, int ns, int na, const double *nodes) {
+  if (!nodes) return NULL;
+  or_mesh *m = mesh_alloc(nx, ny, ns, na);
+  if (!m) return NULL;
+  size_t nn = (size_t)(2 * nx + 1) * (2 * ny + 1);
+  m->iso = 1;
+  m->nx_ = (double *)malloc(sizeof(double) * nn);
+  m->ny_ = (double *)malloc(sizeof(double) * nn);
+  if (!m->nx_ || !m->ny_) {
+    or_mesh_destroy(m);
+    return NULL;
+  }
+  memcpy(m->nx_, nodes, sizeof(double) * nn);
+  memcpy(m->ny_, nodes + nn, sizeof(double) * nn);
+  /* the vertices are the corner nodes */
+  for (int iy = 0; iy <= ny; ++iy)
+    for (int ix = 0; ix <= nx; ++ix) {
+      m->vx[vert_index(m, ix, iy)] = m->nx_[node_index(m, 2 * ix, 2 * iy)];
+      m->vy[vert_index(m, ix, iy)] = m->ny_[node_index(m, 2 * ix, 2 * iy)];
+    }
+  if (mesh_geometry(m) != 0) {
     or_mesh_destroy(m);
     return NULL;
   }
@@ -310,6 +377,8 @@ void or_mesh_destroy(or_mesh *m) {
   free(m->chol);
   free(m->vx);
   free(m->vy);
+  free(m->nx_);
+  free(m->ny_);
   free(m);
 }
 
@@ -669,11 +738,9 @@ static void advect_rate(const or_mesh *m, const double *v, const double *U, doub
     /* cell integral and mass matrix */
     for (int qy = 0; qy < 3; ++qy)
       for (int qx = 0; qx < 3; ++qx) {
-        double xi = gp[qx], eta = gp[qy], w = gw[qx] * gw[qy];
-        double J00 = (1.0 - eta) * (X[1] - X[0]) + eta * (X[3] - X[2]);
-        double J01 = (1.0 - xi) * (X[2] - X[0]) + xi * (X[3] - X[1]);
-        double J10 = (1.0 - eta) * (Y[1] - Y[0]) + eta * (Y[3] - Y[2]);
-        double J11 = (1.0 - xi) * (Y[2] - Y[0]) + xi * (Y[3] - Y[1]);
+        double xi = gp[qx], eta = gp[qy], w = gw[qx] * gw[qy], J[4];
+        map_jacobian(m, (int)e, xi, eta, J);
+        double J00 = J[0], J01 = J[1], J10 = J[2], J11 = J[3];
         double det = J00 * J11 - J01 * J10;
         double ux = 0.0, uy = 0.0;
         for (int a = 0; a < 9; ++a) {
@@ -692,18 +759,28 @@ static void advect_rate(const or_mesh *m, const double *v, const double *U, doub
             M[k * na + l] += w * det * dg_basis(k, xi, eta) * dg_basis(l, xi, eta);
         }
       }
-    /* edge fluxes; scaled outward normal n L = (t_y, -t_x) of the edge vector t */
+    /* edge fluxes; scaled outward normal n L = (t_y, -t_x) of the tangent t =
+     * dx/du of the counter-clockwise edge: the edge vector for the bilinear
+     * map (straight edges), J (dxi/du, deta/du) at the point for the
+     * isoparametric map (curved edges) */
     const int from[4] = {0, 1, 3, 2}, to[4] = {1, 3, 2, 0};
     const int nbx[4] = {0, 1, 0, -1}, nby[4] = {-1, 0, 1, 0};
+    const double dxu[4] = {1.0, 0.0, -1.0, 0.0}, deu[4] = {0.0, 1.0, 0.0, -1.0};
     for (int ed = 0; ed < 4; ++ed) {
       double tx = X[to[ed]] - X[from[ed]], ty = Y[to[ed]] - Y[from[ed]];
-      double nlx = ty, nly = -tx;
       int fx = ex + nbx[ed], fy = ey + nby[ed];
       int has_nb = fx >= 0 && fy >= 0 && fx < m->nx && fy < m->ny;
       size_t f = has_nb ? (size_t)fy * m->nx + fx : 0;
       for (int g = 0; g < 3; ++g) {
         double xi, eta;
         edge_point(ed, gp[g], &xi, &eta);
+        if (m->iso) {
+          double J[4];
+          map_jacobian(m, (int)e, xi, eta, J);
+          tx = J[0] * dxu[ed] + J[1] * deu[ed];
+          ty = J[2] * dxu[ed] + J[3] * deu[ed];
+        }
+        double nlx = ty, nly = -tx;
         double ux = 0.0, uy = 0.0;
         for (int a = 0; a < 9; ++a) {
           double ph = lag2(a % 3, xi) * lag2(a / 3, eta);

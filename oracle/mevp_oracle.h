@@ -57,6 +57,10 @@ typedef struct or_mesh or_mesh;
 /* Mesh and per-element geometry. Returns NULL on invalid arguments
  * (nx, ny < 1; ns not in {3,6,8}; na not in {1,3,6}) or a degenerate element. */
 or_mesh *or_mesh_create(int nx, int ny, int ns, int na, const double *vertices);
+/* The same with the isoparametric CG2 map (reading R8): nodes [2][(2nx+1)(2ny+1)]
+ * are the positions of the CG2 nodes in the node order of v; the vertices are
+ * the corner nodes. */
+or_mesh *or_mesh_create_iso(int nx, int ny, int ns, int na, const double *nodes);
 void or_mesh_destroy(or_mesh *m);
 
 /* Reference-element tables. Sizes: ngp from ns (2 for ns=3, else 3), nG=ngp^2.

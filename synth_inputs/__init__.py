@@ -15,6 +15,7 @@ A ~ U[0.8, 1] per element, a rotating wind gyre of 10 m/s peak and a weak
 
 Layouts (all float64, C order):
   vertices  [2][(ny+1)*(nx+1)]   vertex (ix, iy) at index iy*(nx+1)+ix, metres
+  nodes     [2][(2nx+1)*(2ny+1)] CG2 node positions of a curved mesh, or None
   H, A      [n_a][nx*ny]         element e = ey*nx+ex, DG coefficients
   wind      [2][(2nx+1)*(2ny+1)] CG2 node (ix, iy) at index iy*(2nx+1)+ix, m/s
   ocean     [2][(2nx+1)*(2ny+1)] same
@@ -30,6 +31,7 @@ __all__ = [
     "DomainInputs",
     "uniform_vertices",
     "perturbed_vertices",
+    "curved_nodes",
     "ice_fields",
     "wind_field",
     "ocean_field",
@@ -44,7 +46,8 @@ __all__ = [
 WORKLOAD_SEEDS = {"32x32-dg1": 1001, "256x256-dg2": 1002, "1024x1024-dg2": 1003,
                   "2048x2048-dg2": 1005, "batch64-dg2": 466,
                   "1024x1024-ns8": 1008, "1024x1024-dg2-bilinear": 1009,
-                  "2048x2048-dg2-bilinear": 1010}
+                  "2048x2048-dg2-bilinear": 1010, "256x256-dg2-iso": 1011,
+                  "1024x1024-dg2-iso": 1012}
 
 #: wind gyre peak speed [m/s], angular rotation rate [1/s], ocean peak [m/s]
 WIND_PEAK = 10.0
@@ -64,6 +67,7 @@ class DomainInputs:
     wind: np.ndarray
     ocean: np.ndarray
     meta: dict = field(default_factory=dict)
+    nodes: np.ndarray | None = None  # CG2 node positions of a curved (isoparametric) mesh
 
     @property
     def n_elements(self) -> int:
@@ -105,6 +109,31 @@ def perturbed_vertices(nx: int, ny: int, hx: float, hy: float | None = None,
     V[0] += dx
     V[1] += dy
     return V.reshape(2, -1).copy()
+
+
+def curved_nodes(nx: int, ny: int, hx: float, hy: float | None = None,
+                 amp: float = 0.1, seed: int = 0) -> np.ndarray:
+    """CG2 node positions [2][(2nx+1)(2ny+1)] of a curved mesh: the uniform
+    grid's nodes (cell corners, edge midpoints, centres) moved by a smooth
+    displacement of at most ``amp`` cell widths that also bends the outer
+    boundary, plus a seeded jitter of the interior nodes (0.3 of the smooth
+    amplitude). Cell edges become quadratic curves, so the cells are neither
+    parallelograms nor bilinear images of the square."""
+    hy = hx if hy is None else hy
+    NX, NY = 2 * nx + 1, 2 * ny + 1
+    iy, ix = np.meshgrid(np.arange(NY), np.arange(NX), indexing="ij")
+    xh, yh = ix / (NX - 1), iy / (NY - 1)
+    rng = np.random.default_rng(seed)
+    jx = rng.uniform(-1.0, 1.0, size=xh.shape)
+    jy = rng.uniform(-1.0, 1.0, size=xh.shape)
+    interior = (ix > 0) & (ix < NX - 1) & (iy > 0) & (iy < NY - 1)
+    dx = amp * hx * (0.7 * np.sin(2.0 * math.pi * yh) * np.sin(math.pi * xh + 0.3)
+                     + 0.3 * jx * interior)
+    dy = amp * hy * (0.7 * np.sin(2.0 * math.pi * xh) * np.sin(math.pi * yh + 0.3)
+                     + 0.3 * jy * interior)
+    X = ix * (0.5 * hx) + dx
+    Y = iy * (0.5 * hy) + dy
+    return np.stack([X.ravel(), Y.ravel()]).astype(np.float64)
 
 
 def ice_fields(n_elements: int, n_a: int, seed: int, ho_amp: float = 0.0):
@@ -154,21 +183,30 @@ def ocean_field(nx: int, ny: int) -> np.ndarray:
 def make_domain(nx: int, ny: int, n_s: int, n_a: int = 1, seed: int = 0, *,
                 length: float | None = None, h: float | None = None,
                 perturb: float = 0.0, ho_amp: float = 0.0,
-                wind_phase: float = 0.0) -> DomainInputs:
+                wind_phase: float = 0.0, curved: float = 0.0) -> DomainInputs:
     """One seeded domain. Give either the cell size ``h`` or the domain ``length``
-    (of the x side; cells are square). Default: 512 km domain."""
+    (of the x side; cells are square). Default: 512 km domain. ``perturb``
+    moves the vertices (bilinear cells); ``curved`` instead gives CG2 node
+    positions of a curved mesh (``nodes``; the vertices are its corner nodes)."""
     if h is None:
         length = 512e3 if length is None else length
         h = length / nx
-    if perturb > 0.0:
+    nodes = None
+    if curved > 0.0:
+        nodes = curved_nodes(nx, ny, h, h, amp=curved, seed=seed + 7919)
+        NX = 2 * nx + 1
+        corner = (np.arange(ny + 1)[:, None] * 2 * NX + np.arange(nx + 1)[None, :] * 2).ravel()
+        V = nodes[:, corner].copy()
+    elif perturb > 0.0:
         V = perturbed_vertices(nx, ny, h, h, amp=perturb, seed=seed + 7919)
     else:
         V = uniform_vertices(nx, ny, h, h)
     H, A = ice_fields(nx * ny, n_a, seed, ho_amp=ho_amp)
     return DomainInputs(nx, ny, n_s, n_a, V, H, A,
                         wind_field(nx, ny, phase=wind_phase), ocean_field(nx, ny),
-                        meta={"seed": seed, "h": h, "perturb": perturb,
-                              "ho_amp": ho_amp, "wind_phase": wind_phase})
+                        meta={"seed": seed, "h": h, "perturb": perturb, "curved": curved,
+                              "ho_amp": ho_amp, "wind_phase": wind_phase},
+                        nodes=nodes)
 
 
 def batched_sizes(seed: int = 466, n_domains: int = 64, lo: int = 64, hi: int = 512):
@@ -196,6 +234,8 @@ def named_workload(name: str) -> list[DomainInputs]:
       1024x1024-ns8   1024 x 1024 on 512 km, 8 stress dofs (the Q2-gradient space)
       *-bilinear      the same meshes with interior vertices moved by <= 0.15 h,
                       so every cell is a general quadrilateral
+      *-iso           the same meshes with curved cells: CG2 node positions
+                      moved by <= 0.15 h (isoparametric map)
     """
     seed = WORKLOAD_SEEDS[name]
     if name == "32x32-dg1":
@@ -209,6 +249,8 @@ def named_workload(name: str) -> list[DomainInputs]:
         return [make_domain(n, n, 8, 1, seed)]
     if name.endswith("-bilinear"):
         return [make_domain(n, n, 6, 1, seed, perturb=0.15)]
+    if name.endswith("-iso"):
+        return [make_domain(n, n, 6, 1, seed, curved=0.15)]
     return [make_domain(n, n, 6, 1, seed)]
 
 
