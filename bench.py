@@ -359,7 +359,9 @@ def main():
                 ("batch64-dg2", "fp64", 2, None, None), ("batch64-dg2", "mixed", 2, None, None),
                 ("2048x2048-dg2-bilinear", "fp64", 2, None, None),
                 ("2048x2048-dg2-bilinear", "mixed", 2, None, None),
-                ("1024x1024-ns8", "fp64", 2, None, None)]
+                ("1024x1024-ns8", "fp64", 2, None, None),
+                ("1024x1024-dg2-iso", "fp64", 2, None, None),
+                ("1024x1024-dg2-iso", "mixed", 2, None, None)]
         for wl, prec, st, strat, tl in plan:
             log(f"variant {wl} {prec} {strat or 'tuned'} {tl or ''} ({st} steps)")
             ds = doms if wl == args.workload else named_workload(wl)

@@ -171,6 +171,17 @@ mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params);
  * the element kernel; Sec. 2.1: cells are mapped from a reference element) and
  * waits for the stream to do so. */
 mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy);
+/* Curved cells (Sec. 2.1: the cell map in the velocity's finite element
+ * space): `node_xy` [2][(2nx+1)(2ny+1)] holds the positions of the CG2 nodes in
+ * the node order of v, and every cell of the domain uses the isoparametric map
+ * x(xi, eta) = sum_a X_a phi_a(xi, eta) of its 9 nodes (Jacobian per Gauss
+ * point, local mass matrix per cell, edge normals from the map in
+ * mevp_advect). Replaces a vertex geometry set before (and vice versa); the
+ * corner nodes become the domain's vertices. Stream-ordered copy, then waits
+ * for the stream. With this geometry in a context, FUSED_PAIR and
+ * FUSED_TRIPLE run one subcycle per launch. EINVAL on a bad domain or a NULL
+ * pointer. */
+mevp_status mevp_set_geometry_cg2(mevp_ctx *ctx, int dom, const double *node_xy);
 mevp_status mevp_set_fields(mevp_ctx *ctx, int dom, const double *H, const double *A);
 mevp_status mevp_set_forcing(mevp_ctx *ctx, int dom, const double *wind_xy,
                              const double *ocean_xy);

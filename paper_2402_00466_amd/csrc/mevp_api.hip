@@ -28,9 +28,8 @@ struct mevp_ctx {
   std::vector<DomDev> dom_h;
   std::vector<Blk> eblk_h, nblk_h;
   std::vector<Tile> tiles_h;
-  std::vector<unsigned char> affine;  // per domain: every cell a parallelogram
-  Launch eblk_split{0, 0};            // element blocks: parallelogram domains, then the rest
-  Launch tile_split{0, 0};            // tiles likewise
+  Launch eblk_split{};                // element blocks grouped by geometry kind (GeoKind order)
+  Launch tile_split{};                // tiles likewise
   Tile *tiles_d = nullptr;
   int cur = 0;                        // which of the two v / S buffers holds the state
   mevp_strategy strategy = MEVP_STRATEGY_FUSED;
@@ -102,7 +101,7 @@ KParams derive(const mevp_params &p) {
 
 // Layout of the workspace: offsets in bytes of every array.
 struct Layout {
-  size_t doms, eblk, nblk, tiles, flag, vert, H, A, adv, wind, ocean, v, nc, S, fe, total;
+  size_t doms, eblk, nblk, tiles, flag, vert, xnode, H, A, adv, wind, ocean, v, nc, S, fe, total;
   size_t tot_e, tot_n, tot_v;
   int n_eblk, n_nblk;
   int ns, na;
@@ -149,6 +148,7 @@ mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout
   L->tiles = take(sizeof(Tile) * ntl);
   L->flag = take(sizeof(int) * 4);
   L->vert = take(sizeof(double) * 2 * tv);
+  L->xnode = take(sizeof(double) * 2 * tn);
   L->H = take(sizeof(double) * na * te);
   L->A = take(sizeof(double) * na * te);
   L->adv = take(sizeof(double) * 4 * na * te);
@@ -210,28 +210,25 @@ void graphs_clear(mevp_ctx *c) {
   }
 }
 
-// Element blocks and fused-kernel tiles with the domains of parallelogram
-// cells first (one launch of the constant-Jacobian kernel), then the rest
-// (one launch of the general kernel).
+// Element blocks and fused-kernel tiles grouped by the geometry kind of their
+// domain (GeoKind order: parallelogram, bilinear, isoparametric), one launch of
+// the matching element kernel per non-empty group.
 void order_blocks(mevp_ctx *c) {
   c->eblk_h.clear();
   c->tiles_h.clear();
   const int TX = kTileShapes[c->shape][0] - 1, TY = kTileShapes[c->shape][1] - 1;
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int kind = 0; kind < kNumGeo; ++kind) {
+    const size_t e0 = c->eblk_h.size(), t0 = c->tiles_h.size();
     for (int i = 0; i < c->nd; ++i) {
-      if ((pass == 0) != (c->affine[i] != 0)) continue;
+      if (c->dom_h[i].kind != kind) continue;
       const DomDev &D = c->dom_h[i];
       for (int f = 0; f < D.ne; f += kElemBlock) c->eblk_h.push_back(Blk{i, f});
       for (int y0 = 0; y0 < D.ny; y0 += TY)
         for (int x0 = 0; x0 < D.nx; x0 += TX) c->tiles_h.push_back(Tile{i, x0, y0, 0});
     }
-    if (pass == 0) {
-      c->eblk_split.n_aff = (int)c->eblk_h.size();
-      c->tile_split.n_aff = (int)c->tiles_h.size();
-    }
+    c->eblk_split.n[kind] = (int)(c->eblk_h.size() - e0);
+    c->tile_split.n[kind] = (int)(c->tiles_h.size() - t0);
   }
-  c->eblk_split.n_gen = (int)c->eblk_h.size() - c->eblk_split.n_aff;
-  c->tile_split.n_gen = (int)c->tiles_h.size() - c->tile_split.n_aff;
   // Workgroup i of a launch runs on XCD i % 8. Permute each launch's tiles so
   // that every XCD gets one contiguous band of tiles: neighbouring tiles share
   // halo elements and cache lines, which then meet in the same L2.
@@ -244,8 +241,11 @@ void order_blocks(mevp_ctx *c) {
       start += cnt;
     }
   };
-  xcd_order(c->tiles_h.data(), c->tile_split.n_aff);
-  xcd_order(c->tiles_h.data() + c->tile_split.n_aff, c->tile_split.n_gen);
+  int t0 = 0;
+  for (int kind = 0; kind < kNumGeo; ++kind) {
+    xcd_order(c->tiles_h.data() + t0, c->tile_split.n[kind]);
+    t0 += c->tile_split.n[kind];
+  }
 }
 
 size_t s_words(const mevp_ctx *c) { return (size_t)3 * c->ns * c->tot_e; }
@@ -340,7 +340,6 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
   c->tot_n = L.tot_n;
   c->tot_v = L.tot_v;
   c->geo_set.assign(n_domains, 0);
-  c->affine.assign(n_domains, 0);
   c->fld_set.assign(n_domains, 0);
   c->frc_set.assign(n_domains, 0);
 
@@ -356,6 +355,7 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
     D.elem_off = eo;
     D.node_off = no;
     D.vert_off = vo;
+    D.kind = kGeoBilinear;  // until set_geometry classifies the cells
     eo += D.ne;
     no += D.nn;
     vo += D.nv;
@@ -376,6 +376,7 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
   d.tiles = c->tiles_d;
   d.flag = reinterpret_cast<int *>(base + L.flag);
   d.vert = reinterpret_cast<double *>(base + L.vert);
+  d.xnode = reinterpret_cast<double *>(base + L.xnode);
   d.H = reinterpret_cast<double *>(base + L.H);
   d.A = reinterpret_cast<double *>(base + L.A);
   d.adv = reinterpret_cast<double *>(base + L.adv);
@@ -414,6 +415,22 @@ mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params) {
   return MEVP_OK;
 }
 
+// Record the geometry kind of a domain; when it changes, the domain table,
+// the launch grouping and the captured graphs are rebuilt.
+static mevp_status set_kind(mevp_ctx *ctx, int dom, int kind) {
+  if (ctx->dom_h[dom].kind == kind) return MEVP_OK;
+  hipStream_t s = ctx->stream;
+  graphs_clear(ctx);
+  ctx->dom_h[dom].kind = kind;
+  order_blocks(ctx);
+  mevp_status st = copy(ctx->doms_d, ctx->dom_h.data(), sizeof(DomDev) * ctx->nd, s);
+  if (st == MEVP_OK) st = copy(ctx->eblk_d, ctx->eblk_h.data(), sizeof(Blk) * ctx->eblk_h.size(), s);
+  if (st == MEVP_OK) st = copy(ctx->tiles_d, ctx->tiles_h.data(), sizeof(Tile) * ctx->tiles_h.size(), s);
+  // the host tables must outlive the asynchronous copies
+  if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(s));
+  return st;
+}
+
 mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy) {
   if (bad_dom(ctx, dom) || !vertex_xy) return MEVP_EINVAL;
   const DomDev &D = ctx->dom_h[dom];
@@ -427,18 +444,23 @@ mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy) {
   int aff = 0;
   if (st == MEVP_OK) st = hip_status(hipMemcpyAsync(&aff, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(s));
-  if (st != MEVP_OK) return st;
-  if ((aff != 0) != (ctx->affine[dom] != 0)) {
-    graphs_clear(ctx);  // launch split changes
-    ctx->affine[dom] = aff != 0;
-    order_blocks(ctx);
-    st = copy(ctx->eblk_d, ctx->eblk_h.data(), sizeof(Blk) * ctx->eblk_h.size(), s);
-    if (st == MEVP_OK) st = copy(ctx->tiles_d, ctx->tiles_h.data(), sizeof(Tile) * ctx->tiles_h.size(), s);
-    if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(s));
-    if (st != MEVP_OK) return st;
-  }
-  ctx->geo_set[dom] = 1;
-  return MEVP_OK;
+  if (st == MEVP_OK) st = set_kind(ctx, dom, aff ? kGeoAffine : kGeoBilinear);
+  if (st == MEVP_OK) ctx->geo_set[dom] = 1;
+  return st;
+}
+
+mevp_status mevp_set_geometry_cg2(mevp_ctx *ctx, int dom, const double *node_xy) {
+  if (bad_dom(ctx, dom) || !node_xy) return MEVP_EINVAL;
+  const DomDev &D = ctx->dom_h[dom];
+  hipStream_t s = ctx->stream;
+  mevp_status st = copy(const_cast<double *>(ctx->d.xnode) + 2 * (size_t)D.node_off, node_xy,
+                        sizeof(double) * 2 * D.nn, s);
+  // the vertices (corner nodes) are kept for the input checks
+  if (st == MEVP_OK) st = hip_status(launch_corner_vertices(ctx->d, dom, D.nv, s));
+  if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(s));
+  if (st == MEVP_OK) st = set_kind(ctx, dom, kGeoIso);
+  if (st == MEVP_OK) ctx->geo_set[dom] = 1;
+  return st;
 }
 
 mevp_status mevp_set_fields(mevp_ctx *ctx, int dom, const double *H, const double *A) {
@@ -536,8 +558,9 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
   if (n == 0) return MEVP_OK;
   // persistent: one cooperative launch for all n subcycles, when every tile
   // takes the same kernel (all parallelogram domains, or none)
-  if (ctx->strategy == MEVP_STRATEGY_PERSISTENT &&
-      (ctx->tile_split.n_aff == 0 || ctx->tile_split.n_gen == 0)) {
+  int kinds = 0;
+  for (int k = 0; k < kNumGeo; ++k) kinds += ctx->tile_split.n[k] > 0;
+  if (ctx->strategy == MEVP_STRATEGY_PERSISTENT && kinds == 1) {
     const int nxt = ctx->cur ^ 1;
     FusedArgs f;
     f.b0 = Bufs{v_buf(ctx, ctx->cur), v_buf(ctx, nxt), S_buf(ctx, ctx->cur), S_buf(ctx, nxt)};
@@ -562,11 +585,14 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
     if (ctx->strategy != MEVP_STRATEGY_TWO_PHASE) {
       // FUSED_PAIR / FUSED_TRIPLE: 2 / 3 subcycles per launch while that many
       // remain, then the rest in one launch
-      // (three per launch exist for parallelogram cells only: with any general
-      // domain FUSED_TRIPLE runs two per launch)
-      const int most = ctx->strategy == MEVP_STRATEGY_FUSED_TRIPLE
-                           ? (ctx->tile_split.n_gen == 0 ? 3 : 2)
-                       : ctx->strategy == MEVP_STRATEGY_FUSED_PAIR ? 2 : 1;
+      // (three per launch exist for parallelogram cells only: with a bilinear
+      // domain FUSED_TRIPLE runs two per launch; with an isoparametric domain
+      // both run one per launch)
+      const Launch &ts = ctx->tile_split;
+      int most = ctx->strategy == MEVP_STRATEGY_FUSED_TRIPLE ? 3
+                 : ctx->strategy == MEVP_STRATEGY_FUSED_PAIR ? 2 : 1;
+      if (most == 3 && ts.n[kGeoBilinear] > 0) most = 2;
+      if (ts.n[kGeoIso] > 0) most = 1;
       const int depth = most < n - it ? most : n - it;
       const int nxt = ctx->cur ^ 1;
       FusedArgs f;
@@ -756,6 +782,7 @@ mevp_status mevp_check_inputs(mevp_ctx *ctx) {
   mevp_status st = hip_status(launch_fill(ctx->d.flag, 1, 0u, s));
   const size_t te = ctx->tot_e, tn = ctx->tot_n;
   if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.vert, 2 * ctx->tot_v, ctx->d.flag, 1, s));
+  if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.xnode, 2 * tn, ctx->d.flag, 1, s));
   if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.H, ctx->na * te, ctx->d.flag, 1, s));
   if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.A, ctx->na * te, ctx->d.flag, 1, s));
   if (st == MEVP_OK) st = hip_status(launch_check_finite(ctx->d.wind, 2 * tn, ctx->d.flag, 1, s));
@@ -832,9 +859,13 @@ static std::string tune_key(const mevp_ctx *c) {
     if (d.nx > mx) mx = d.nx;
     if (d.ny > my) my = d.ny;
   }
-  char buf[160];
-  snprintf(buf, sizeof buf, "gfx950/%s/ns%d/na%d/dom%d/el%lld/max%lldx%lld",
-           c->prec == MEVP_MIXED ? "mixed" : "fp64", c->ns, c->na, c->nd, ne, mx, my);
+  // elements per geometry kind (parallelogram, bilinear, isoparametric)
+  long long ek[kNumGeo] = {0, 0, 0};
+  for (const auto &D : c->dom_h) ek[D.kind] += D.ne;
+  char buf[200];
+  snprintf(buf, sizeof buf, "gfx950/%s/ns%d/na%d/dom%d/el%lld/max%lldx%lld/geo%lld.%lld.%lld",
+           c->prec == MEVP_MIXED ? "mixed" : "fp64", c->ns, c->na, c->nd, ne, mx, my, ek[0], ek[1],
+           ek[2]);
   return buf;
 }
 

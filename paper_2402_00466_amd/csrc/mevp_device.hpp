@@ -71,8 +71,8 @@ template <int NS, class T>
 struct Ldl {
   T L[NS][NS];
   T invd[NS];
-  template <class Q>
-  __device__ __forceinline__ void build(const Cell<T> &c) {
+  template <class Q, class Map>
+  __device__ __forceinline__ void build(const Map &c) {
     T M[NS][NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k)
@@ -193,6 +193,41 @@ __device__ __forceinline__ void load_velocity(const DomDev &D, const double *v, 
   gather_velocity<T>(vxg, vxg + D.nn, 2 * ey * NX + 2 * ex, NX, vx, vy);
 }
 
+// Isoparametric cell map: x(xi, eta) = sum_a X_a phi_a(xi, eta) over the 9
+// CG2 nodes (positions relative to local node 0, so that the float variant
+// keeps the Jacobian free of cancellation); J from the same reference
+// derivative tables as the velocity gradient.
+template <class T>
+struct Q2Map {
+  T x[9], y[9];
+  __device__ __forceinline__ void jac(double xi, double eta, T &J00, T &J01, T &J10,
+                                      T &J11) const {
+    J00 = J01 = J10 = J11 = T(0);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      const double dx = q2_1d_d(a % 3, xi) * q2_1d(a / 3, eta);
+      const double dy = q2_1d(a % 3, xi) * q2_1d_d(a / 3, eta);
+      if (dx != 0.0) {
+        J00 += T(dx) * x[a];
+        J10 += T(dx) * y[a];
+      }
+      if (dy != 0.0) {
+        J01 += T(dy) * x[a];
+        J11 += T(dy) * y[a];
+      }
+    }
+  }
+};
+
+template <class T>
+__device__ __forceinline__ Q2Map<T> load_q2map(const DomDev &D, const double *xnode, int ex,
+                                               int ey) {
+  const double *XN = xnode + 2 * (size_t)D.node_off;
+  Q2Map<T> m;
+  gather_velocity<T>(XN, XN + D.nn, 2 * ey * (2 * D.nx + 1) + 2 * ex, 2 * D.nx + 1, m.x, m.y);
+  return m;
+}
+
 template <int NA>
 __device__ __forceinline__ void load_ice(const DevArrays &d, const DomDev &D, int el,
                                          double (&Hc)[NA], double (&Ac)[NA]) {
@@ -293,33 +328,39 @@ struct DgGauss {
 // Geometry of one element as the element update needs it: the constant
 // Jacobian of a parallelogram cell, or the bilinear map of a general cell.
 // ---------------------------------------------------------------------------
-template <class T, bool AFF>
+template <class T, int GK>
 struct Geo;
 template <class T>
-struct Geo<T, true> {
+struct Geo<T, kGeoAffine> {
   T J00, J01, J10, J11;
 };
 template <class T>
-struct Geo<T, false> {
-  Cell<T> cell;
+struct Geo<T, kGeoBilinear> {
+  Cell<T> map;
+};
+template <class T>
+struct Geo<T, kGeoIso> {
+  Q2Map<T> map;
 };
 
-template <class T, bool AFF>
-__device__ __forceinline__ Geo<T, AFF> load_geo(const DevArrays &d, const DomDev &D, int ex,
-                                                int ey) {
-  if constexpr (AFF) {
+template <class T, int GK>
+__device__ __forceinline__ Geo<T, GK> load_geo(const DevArrays &d, const DomDev &D, int ex,
+                                               int ey) {
+  if constexpr (GK == kGeoAffine) {
     const double *VX = d.vert + 2 * (size_t)D.vert_off;
     const double *VY = VX + D.nv;
     const int i0 = ey * (D.nx + 1) + ex, i2 = i0 + D.nx + 1;
     const double X0 = VX[i0], Y0 = VY[i0];
-    Geo<T, true> g;
+    Geo<T, kGeoAffine> g;
     g.J00 = T(VX[i0 + 1] - X0);
     g.J10 = T(VY[i0 + 1] - Y0);
     g.J01 = T(VX[i2] - X0);
     g.J11 = T(VY[i2] - Y0);
     return g;
+  } else if constexpr (GK == kGeoBilinear) {
+    return Geo<T, kGeoBilinear>{load_cell<T>(D, d.vert, ex, ey)};
   } else {
-    return Geo<T, false>{load_cell<T>(D, d.vert, ex, ey)};
+    return Geo<T, kGeoIso>{load_q2map<T>(D, d.xnode, ex, ey)};
   }
 }
 
@@ -336,7 +377,7 @@ __device__ __forceinline__ Geo<T, AFF> load_geo(const DevArrays &d, const DomDev
 // coefficients and fx, fy the forces.
 // ---------------------------------------------------------------------------
 template <int NS, int NA, class T, class SOld>
-__device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, true> &g,
+__device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kGeoAffine> &g,
                                                const double (&Hc)[NA], const double (&Ac)[NA],
                                                const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
@@ -424,19 +465,18 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, tr
 }
 
 // ---------------------------------------------------------------------------
-// Element update, general bilinear cells: Jacobian per Gauss point, local
-// mass matrix M_e = Psi W_e Psi^T factorised per element. Same inputs and
-// outputs as element_affine.
+// Element update, general cells (bilinear or isoparametric map): Jacobian per
+// Gauss point from the map, local mass matrix M_e = Psi W_e Psi^T factorised
+// per element. Same inputs and outputs as element_affine.
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class SOld>
-__device__ __forceinline__ void element_general(const KParams &p, const Geo<T, false> &g,
+template <int NS, int NA, class T, class Map, class SOld>
+__device__ __forceinline__ void element_general(const KParams &p, const Map &cell,
                                                 const double (&Hc)[NA], const double (&Ac)[NA],
                                                 const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                 T (&fx)[9], T (&fy)[9]) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
-  const Cell<T> &cell = g.cell;
   Ldl<NS, T> mass;
   mass.template build<Q>(cell);
 
@@ -539,34 +579,34 @@ __device__ __forceinline__ void element_general(const KParams &p, const Geo<T, f
   }
 }
 
-template <int NS, int NA, class T, bool AFF, class SOld>
-__device__ __forceinline__ void element_compute(const KParams &p, const Geo<T, AFF> &g,
+template <int NS, int NA, class T, int GK, class SOld>
+__device__ __forceinline__ void element_compute(const KParams &p, const Geo<T, GK> &g,
                                                 const double (&Hc)[NA], const double (&Ac)[NA],
                                                 const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                 T (&fx)[9], T (&fy)[9]) {
-  if constexpr (AFF)
+  if constexpr (GK == kGeoAffine)
     element_affine<NS, NA, T>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
   else
-    element_general<NS, NA, T>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+    element_general<NS, NA, T>(p, g.map, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
 // Element update of element el = (ex, ey) with every input read from global
 // memory (v and S of the current subcycle).
-template <int NS, int NA, class T, class TS, bool AFF>
+template <int NS, int NA, class T, class TS, int GK>
 __device__ __forceinline__ void element_update(const DevArrays &d, const DomDev &D,
                                                const KParams &p, const double *v_in,
                                                const TS *S_in, int el, int ex, int ey,
                                                T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                T (&fx)[9], T (&fy)[9]) {
-  const Geo<T, AFF> g = load_geo<T, AFF>(d, D, ex, ey);
+  const Geo<T, GK> g = load_geo<T, GK>(d, D, ex, ey);
   T vx[9], vy[9];
   load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
   double Hc[NA], Ac[NA];
   load_ice<NA>(d, D, el, Hc, Ac);
   const size_t ne = (size_t)D.ne;
   auto sold = [&](int c, int k) { return T(S_in[(c * NS + k) * ne + el]); };
-  element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+  element_compute<NS, NA, T, GK>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
 // Velocity update of one interior node:
@@ -611,7 +651,7 @@ __device__ __forceinline__ void velocity_update6(const KParams &p, const double 
 // Two-phase subcycle, element kernel: element update, S written in place
 // (each lane reads and writes only its own element), forces to scratch.
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class TS, bool AFF>
+template <int NS, int NA, class T, class TS, int GK>
 __global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p, const Blk *blks,
                                                         Bufs b) {
   const Blk blk = blks[blockIdx.x];
@@ -621,7 +661,7 @@ __global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p, 
   const int ex = el % D.nx, ey = el / D.nx;
   const DomBufs<TS> B(b, D, NS);
   T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
-  element_update<NS, NA, T, TS, AFF>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx, fy);
+  element_update<NS, NA, T, TS, GK>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx, fy);
   store_stress<NS, T, TS>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
   const size_t ne = (size_t)D.ne;
   TS *fe = static_cast<TS *>(d.fe) + (size_t)18 * D.elem_off;
@@ -757,7 +797,7 @@ __device__ __forceinline__ void update_nodes(const KParams &p, const DomDev &D, 
 // buffers and written to the *_out buffers (double buffering: neighbouring
 // tiles read the old values while this one writes the new).
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class TS, bool AFF, int EX, int EY>
+template <int NS, int NA, class T, class TS, int GK, int EX, int EY>
 __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p, const Tile t,
                                            const Bufs &b, T (*fl)[EX * EY]) {
   constexpr int TX = EX - 1, TY = EY - 1, NT = EX * EY;
@@ -770,8 +810,8 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
     if (ex >= 0 && ey >= 0 && ex < D.nx && ey < D.ny) {
       const int el = ey * D.nx + ex;
       T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
-      element_update<NS, NA, T, TS, AFF>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx,
-                                         fy);
+      element_update<NS, NA, T, TS, GK>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx,
+                                        fy);
       if (lx > 0 && ly > 0) store_stress<NS, T, TS>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
@@ -816,7 +856,7 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
 // equals K single subcycles bit for bit. Only v^{p-1} / S^{p-1} are read
 // and only v^{p+K-1} / S^{p+K-1} written (double buffering as in fused_tile).
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class TS, bool AFF, int EX, int EY, int K>
+template <int NS, int NA, class T, class TS, int GK, int EX, int EY, int K>
 __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
     k_fused_multi(DevArrays d, KParams p, const Tile *tiles, Bufs b) {
   static_assert(K == 2 || K == 3, "two or three subcycles per pass");
@@ -840,7 +880,7 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
   const bool exists = ex >= 0 && ey >= 0 && ex < D.nx && ey < D.ny;
   const int el = exists ? ey * D.nx + ex : 0;
 
-  Geo<T, AFF> g{};
+  Geo<T, GK> g{};
   double Hc[NA], Ac[NA];
   T S11[NS], S12[NS], S22[NS];  // the lane's stress, as stored (rounded to TS)
   auto vlds = [&](int ix, int iy) { return (iy - jy0) * VW + (ix - jx0); };
@@ -851,15 +891,15 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
       T vx[9], vy[9];
       T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
       if (i == 0) {
-        g = load_geo<T, AFF>(d, D, ex, ey);
+        g = load_geo<T, GK>(d, D, ex, ey);
         load_ice<NA>(d, D, el, Hc, Ac);
         load_velocity<T>(D, B.v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
         auto sold = [&](int c, int k) { return T(B.S_in[(c * NS + k) * ne + el]); };
-        element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+        element_compute<NS, NA, T, GK>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
       } else {
         gather_velocity<T>(vl[0], vl[1], vlds(2 * ex, 2 * ey), VW, vx, vy);
         auto sold = [&](int c, int k) { return c == 0 ? S11[k] : c == 1 ? S12[k] : S22[k]; };
-        element_compute<NS, NA, T, AFF>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+        element_compute<NS, NA, T, GK>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
       }
       if (i == K - 1) {
         if (lx >= K && ly >= K) store_stress<NS, T, TS>(B.S_out, ne, el, R11, R12, R22);
@@ -933,20 +973,20 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
 // tile table), with buffers b0 for even i and b1 (= b0 swapped) for odd i,
 // and a grid-wide barrier between subcycles. Every workgroup runs the same
 // number of barriers, so the grid always drains.
-template <int NS, int NA, class T, class TS, bool AFF, int EX, int EY>
+template <int NS, int NA, class T, class TS, int GK, int EX, int EY>
 __global__ void __launch_bounds__(EX *EY) k_fused(DevArrays d, KParams p, const Tile *tiles,
                                                    int ntiles, Bufs b0, Bufs b1, int n_sub,
                                                    int persist) {
   __shared__ T fl[18][EX * EY];
   if (!persist) {
-    fused_tile<NS, NA, T, TS, AFF, EX, EY>(d, p, tiles[blockIdx.x], b0, fl);
+    fused_tile<NS, NA, T, TS, GK, EX, EY>(d, p, tiles[blockIdx.x], b0, fl);
     return;
   }
   cooperative_groups::grid_group g = cooperative_groups::this_grid();
   for (int it = 0; it < n_sub; ++it) {
     const Bufs &b = (it & 1) ? b1 : b0;
     for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
-      fused_tile<NS, NA, T, TS, AFF, EX, EY>(d, p, tiles[i], b, fl);
+      fused_tile<NS, NA, T, TS, GK, EX, EY>(d, p, tiles[i], b, fl);
       __syncthreads();  // the next tile reuses the LDS
     }
     if (it + 1 < n_sub) g.sync();
@@ -986,38 +1026,44 @@ __global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams 
       const int cc = ix - 2 * ex;
       const int a = 3 * b + cc;
       const size_t e = (size_t)ey * D.nx + ex;
-      const Cell<double> cell = load_cell<double>(D, d.vert, ex, ey);
       double Hc[NA], Ac[NA];
 #pragma unroll
       for (int k = 0; k < NA; ++k) {
         Hc[k] = Hd[k * ne + e];
         Ac[k] = Ad[k * ne + e];
       }
-      double sh = 0.0, sa = 0.0;
+      // int rho_i h phi_a and int a phi_a over the element, for its cell map
+      auto integrals = [&](const auto &cell) {
+        double sh = 0.0, sa = 0.0;
 #pragma unroll
-      for (int q = 0; q < Q::NG; ++q) {
-        double J00, J01, J10, J11;
-        cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
-        const double wd = Q::w(q) * (J00 * J11 - J01 * J10);
-        double hs = 0.0, as = 0.0;
+        for (int q = 0; q < Q::NG; ++q) {
+          double J00, J01, J10, J11;
+          cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+          const double wd = Q::w(q) * (J00 * J11 - J01 * J10);
+          double hs = 0.0, as = 0.0;
 #pragma unroll
-        for (int k = 0; k < NA; ++k) {
-          hs += Hc[k] * Q::psi(k, q);
-          as += Ac[k] * Q::psi(k, q);
-        }
-        const double h = fmax(0.0, hs), ac = fmin(1.0, fmax(0.0, as));
-        double phi = 0.0;
-        switch (a) {  // keep the table lookup a constant per branch
+          for (int k = 0; k < NA; ++k) {
+            hs += Hc[k] * Q::psi(k, q);
+            as += Ac[k] * Q::psi(k, q);
+          }
+          const double h = fmax(0.0, hs), ac = fmin(1.0, fmax(0.0, as));
+          double phi = 0.0;
+          switch (a) {  // keep the table lookup a constant per branch
 #define MEVP_PHI_CASE(A_) case A_: phi = Q::phi(A_, q); break;
-          MEVP_PHI_CASE(0) MEVP_PHI_CASE(1) MEVP_PHI_CASE(2) MEVP_PHI_CASE(3) MEVP_PHI_CASE(4)
-          MEVP_PHI_CASE(5) MEVP_PHI_CASE(6) MEVP_PHI_CASE(7) MEVP_PHI_CASE(8)
+            MEVP_PHI_CASE(0) MEVP_PHI_CASE(1) MEVP_PHI_CASE(2) MEVP_PHI_CASE(3) MEVP_PHI_CASE(4)
+            MEVP_PHI_CASE(5) MEVP_PHI_CASE(6) MEVP_PHI_CASE(7) MEVP_PHI_CASE(8)
 #undef MEVP_PHI_CASE
+          }
+          sh += wd * p.rho_i * h * phi;
+          sa += wd * ac * phi;
         }
-        sh += wd * p.rho_i * h * phi;
-        sa += wd * ac * phi;
-      }
-      MH += sh;
-      mA += sa;
+        MH += sh;
+        mA += sa;
+      };
+      if (D.kind == kGeoIso)
+        integrals(load_q2map<double>(D, d.xnode, ex, ey));
+      else
+        integrals(load_cell<double>(D, d.vert, ex, ey));
     }
   }
   const double wx = d.wind[o + j], wy = d.wind[o + D.nn + j];
@@ -1091,6 +1137,14 @@ __device__ __forceinline__ void cg2_eval(const double (&vx)[9], const double (&v
   }
 }
 
+template <int NA, class Map>
+__device__ __forceinline__ void advect_element(const DevArrays &d, const DomDev &D, const Map &cell,
+                                               bool curved, int el, int ex, int ey,
+                                               const double *v, const double *Hn,
+                                               const double *An, const double *Hin,
+                                               const double *Ain, double *Hout, double *Aout,
+                                               double dt, double ca, double cb);
+
 template <int NA>
 __global__ void __launch_bounds__(kElemBlock) k_advect(DevArrays d, const Blk *blks,
                                                        const double *v, const double *Hn,
@@ -1103,8 +1157,24 @@ __global__ void __launch_bounds__(kElemBlock) k_advect(DevArrays d, const Blk *b
   const int el = blk.first + (int)threadIdx.x;
   if (el >= D.ne) return;
   const int ex = el % D.nx, ey = el / D.nx;
+  if (D.kind == kGeoIso)
+    advect_element<NA>(d, D, load_q2map<double>(D, d.xnode, ex, ey), true, el, ex, ey, v, Hn,
+                       An, Hin, Ain, Hout, Aout, dt, ca, cb);
+  else
+    advect_element<NA>(d, D, load_cell<double>(D, d.vert, ex, ey), false, el, ex, ey, v, Hn, An,
+                       Hin, Ain, Hout, Aout, dt, ca, cb);
+}
+
+// One stage for element el with cell map `cell`; curved: edge normals from
+// the map's tangent at each edge point, else from the edge vector.
+template <int NA, class Map>
+__device__ __forceinline__ void advect_element(const DevArrays &d, const DomDev &D, const Map &cell,
+                                               bool curved, int el, int ex, int ey,
+                                               const double *v, const double *Hn,
+                                               const double *An, const double *Hin,
+                                               const double *Ain, double *Hout, double *Aout,
+                                               double dt, double ca, double cb) {
   const size_t ne = (size_t)D.ne, off = (size_t)NA * D.elem_off;
-  const Cell<double> cell = load_cell<double>(D, d.vert, ex, ey);
   double vx[9], vy[9];
   load_velocity<double>(D, v, ex, ey, vx, vy);
   double Ue[2][NA];
@@ -1151,11 +1221,11 @@ __global__ void __launch_bounds__(kElemBlock) k_advect(DevArrays d, const Blk *b
   const int vid[4] = {i0, i0 + 1, i2, i2 + 1};
   const int from[4] = {0, 1, 3, 2}, to[4] = {1, 3, 2, 0};
   const int ddx[4] = {0, 1, 0, -1}, ddy[4] = {-1, 0, 1, 0};
+  const double dxu[4] = {1.0, 0.0, -1.0, 0.0}, deu[4] = {0.0, 1.0, 0.0, -1.0};
 #pragma unroll
   for (int ed = 0; ed < 4; ++ed) {
-    const double tx = VX[vid[to[ed]]] - VX[vid[from[ed]]];
-    const double ty = VY[vid[to[ed]]] - VY[vid[from[ed]]];
-    const double nlx = ty, nly = -tx;  // outward normal times edge length
+    const double ex_t = VX[vid[to[ed]]] - VX[vid[from[ed]]];
+    const double ey_t = VY[vid[to[ed]]] - VY[vid[from[ed]]];
     const int fx = ex + ddx[ed], fy = ey + ddy[ed];
     const bool nb = fx >= 0 && fy >= 0 && fx < D.nx && fy < D.ny;
     double Un[2][NA];
@@ -1170,6 +1240,16 @@ __global__ void __launch_bounds__(kElemBlock) k_advect(DevArrays d, const Blk *b
       const double u = kAdvX[g];
       const double xi = ed == 0 ? u : ed == 1 ? 1.0 : ed == 2 ? 1.0 - u : 0.0;
       const double eta = ed == 0 ? 0.0 : ed == 1 ? u : ed == 2 ? 1.0 : 1.0 - u;
+      // outward normal times the edge's length element: (t_y, -t_x) of the
+      // tangent t = dx/du along the counter-clockwise edge
+      double tx = ex_t, ty = ey_t;
+      if (curved) {
+        double J00, J01, J10, J11;
+        cell.jac(xi, eta, J00, J01, J10, J11);
+        tx = J00 * dxu[ed] + J01 * deu[ed];
+        ty = J10 * dxu[ed] + J11 * deu[ed];
+      }
+      const double nlx = ty, nly = -tx;
       double ux, uy;
       cg2_eval(vx, vy, xi, eta, ux, uy);
       const double vn = ux * nlx + uy * nly;
@@ -1242,41 +1322,51 @@ inline hipError_t begin_step_t(const DevArrays &d, const KParams &p, const doubl
   return hipGetLastError();
 }
 
-// Two-phase subcycle: element kernel(s) (parallelogram blocks, general
-// blocks), then the node kernel.
+// Two-phase subcycle: element kernel(s) per geometry kind, then the node kernel.
 template <int NS, int NA, class T>
 inline hipError_t two_phase_t(const DevArrays &d, const KParams &p, const Launch &L, Bufs b,
                               hipStream_t s) {
-  if (L.n_aff > 0)
-    hipLaunchKernelGGL((k_element<NS, NA, T, T, true>), dim3(L.n_aff), dim3(kElemBlock), 0, s, d, p,
-                       d.eblk, b);
-  if (L.n_gen > 0)
-    hipLaunchKernelGGL((k_element<NS, NA, T, T, false>), dim3(L.n_gen), dim3(kElemBlock), 0, s, d, p,
-                       d.eblk + L.n_aff, b);
+  const Blk *blk = d.eblk;
+  if (L.n[kGeoAffine] > 0)
+    hipLaunchKernelGGL((k_element<NS, NA, T, T, kGeoAffine>), dim3(L.n[kGeoAffine]),
+                       dim3(kElemBlock), 0, s, d, p, blk, b);
+  blk += L.n[kGeoAffine];
+  if (L.n[kGeoBilinear] > 0)
+    hipLaunchKernelGGL((k_element<NS, NA, T, T, kGeoBilinear>), dim3(L.n[kGeoBilinear]),
+                       dim3(kElemBlock), 0, s, d, p, blk, b);
+  blk += L.n[kGeoBilinear];
+  if (L.n[kGeoIso] > 0)
+    hipLaunchKernelGGL((k_element<NS, NA, T, T, kGeoIso>), dim3(L.n[kGeoIso]), dim3(kElemBlock),
+                       0, s, d, p, blk, b);
   return hipGetLastError();
 }
 
-// Fused subcycle(s): tile kernel(s), parallelogram tiles first; f.depth 2 or 3:
+// Fused subcycle(s): tile kernel(s) per geometry kind, in GeoKind order; f.depth 2 or 3:
 // the kernel that runs that many subcycles per pass.
-template <int NS, int NA, class T, bool AFF, int EX, int EY>
+template <int NS, int NA, class T, int GK, int EX, int EY>
 inline hipError_t fused_one(const DevArrays &d, const KParams &p, const Tile *tiles, int ntiles,
                             const FusedArgs &f, hipStream_t s) {
   if (f.depth == 2) {
-    hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, AFF, EX, EY, 2>), dim3(ntiles),
-                       dim3((EX + 2) * (EY + 2)), 0, s, d, p, tiles, f.b0);
-    return hipGetLastError();
+    // two subcycles per pass: parallelogram and bilinear cells (the
+    // isoparametric map's 18 coordinates per lane do not fit beside them)
+    if constexpr (GK != kGeoIso) {
+      hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, GK, EX, EY, 2>), dim3(ntiles),
+                         dim3((EX + 2) * (EY + 2)), 0, s, d, p, tiles, f.b0);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
   }
   if (f.depth == 3) {
     // three subcycles per pass: built for parallelogram cells and one ice dof
     // only (the general-cell update would spill at this occupancy)
-    if constexpr (NA == 1 && AFF) {
-      hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, AFF, EX, EY, 3>), dim3(ntiles),
+    if constexpr (NA == 1 && GK == kGeoAffine) {
+      hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, GK, EX, EY, 3>), dim3(ntiles),
                          dim3((EX + 4) * (EY + 4)), 0, s, d, p, tiles, f.b0);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
   }
-  auto kern = k_fused<NS, NA, T, T, AFF, EX, EY>;
+  auto kern = k_fused<NS, NA, T, T, GK, EX, EY>;
   if (!f.persist) {
     hipLaunchKernelGGL(kern, dim3(ntiles), dim3(EX * EY), 0, s, d, p, tiles, ntiles, f.b0, f.b1, 1, 0);
     return hipGetLastError();
@@ -1304,9 +1394,15 @@ template <int NS, int NA, class T, int EX, int EY>
 inline hipError_t fused_shape(const DevArrays &d, const KParams &p, const Launch &L,
                               const FusedArgs &f, hipStream_t s) {
   hipError_t e = hipSuccess;
-  if (L.n_aff > 0) e = fused_one<NS, NA, T, true, EX, EY>(d, p, d.tiles, L.n_aff, f, s);
-  if (e == hipSuccess && L.n_gen > 0)
-    e = fused_one<NS, NA, T, false, EX, EY>(d, p, d.tiles + L.n_aff, L.n_gen, f, s);
+  const Tile *t = d.tiles;
+  if (L.n[kGeoAffine] > 0)
+    e = fused_one<NS, NA, T, kGeoAffine, EX, EY>(d, p, t, L.n[kGeoAffine], f, s);
+  t += L.n[kGeoAffine];
+  if (e == hipSuccess && L.n[kGeoBilinear] > 0)
+    e = fused_one<NS, NA, T, kGeoBilinear, EX, EY>(d, p, t, L.n[kGeoBilinear], f, s);
+  t += L.n[kGeoBilinear];
+  if (e == hipSuccess && L.n[kGeoIso] > 0)
+    e = fused_one<NS, NA, T, kGeoIso, EX, EY>(d, p, t, L.n[kGeoIso], f, s);
   return e;
 }
 

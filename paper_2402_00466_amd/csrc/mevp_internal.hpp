@@ -16,7 +16,14 @@ struct DomDev {
   int elem_off;        // first element of this domain in the context
   int node_off;        // first node
   int vert_off;        // first vertex
+  int kind;            // cell geometry, a GeoKind
 };
+
+// Cell geometry of a domain, which picks the element update: parallelogram
+// cells (constant Jacobian), bilinear map of the 4 vertices, isoparametric
+// map of the 9 CG2 nodes (curved cells).
+enum GeoKind { kGeoAffine = 0, kGeoBilinear = 1, kGeoIso = 2 };
+constexpr int kNumGeo = 3;
 
 // A block of work: domain index and the first local element (or node).
 struct Blk {
@@ -49,9 +56,10 @@ struct FusedArgs {
   int depth;       // subcycles per launch of k_fused_multi (2, 3; buffers b0), else 1
 };
 
-// Leading blocks (or tiles) of parallelogram-cell domains, then the rest.
+// Blocks (or tiles) grouped by the geometry kind of their domain, in GeoKind
+// order: n[k] of kind k.
 struct Launch {
-  int n_aff, n_gen;
+  int n[kNumGeo];
 };
 
 // Scalars the kernels need, derived once from mevp_params on the host.
@@ -69,6 +77,7 @@ struct DevArrays {
   const Blk *nblk;  // node blocks
   const Tile *tiles;  // fused-kernel tiles: parallelogram-cell domains first
   const double *vert;  // [dom][2][nv]
+  const double *xnode; // [dom][2][nn] CG2 node positions (isoparametric domains)
   const double *H;     // [dom][n_a][ne]
   const double *A;
   double *adv;         // advection stages: [4][dom][n_a][ne] (H1, A1, H2, A2)
@@ -102,6 +111,7 @@ hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, i
 hipError_t launch_fused_subcycle(const DevArrays &d, const KParams &p, int n_s, int n_a,
                                  bool mixed, const Launch &L, const FusedArgs &f, hipStream_t s);
 hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s);
+hipError_t launch_corner_vertices(const DevArrays &d, int dom, int nv, hipStream_t s);
 hipError_t launch_advect_stage(const DevArrays &d, int n_a, int n_eblk, const double *v,
                                const double *Hn, const double *An, const double *Hin,
                                const double *Ain, double *Hout, double *Aout, double dt, double ca,

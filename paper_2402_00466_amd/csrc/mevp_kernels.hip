@@ -38,15 +38,34 @@ __global__ void __launch_bounds__(kElemBlock) k_check_jacobian(DevArrays d, int 
   const DomDev D = d.doms[blk.dom];
   const int el = blk.first + (int)threadIdx.x;
   if (el >= D.ne) return;
-  const Cell<double> c = load_cell<double>(D, d.vert, el % D.nx, el / D.nx);
   bool bad = false;
+  auto check = [&](const auto &c) {
 #pragma unroll
-  for (int q = 0; q < Q::NG; ++q) {
-    double J00, J01, J10, J11;
-    c.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
-    bad |= !(J00 * J11 - J01 * J10 > 0.0);
-  }
+    for (int q = 0; q < Q::NG; ++q) {
+      double J00, J01, J10, J11;
+      c.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+      bad |= !(J00 * J11 - J01 * J10 > 0.0);
+    }
+  };
+  if (D.kind == kGeoIso)
+    check(load_q2map<double>(D, d.xnode, el % D.nx, el / D.nx));
+  else
+    check(load_cell<double>(D, d.vert, el % D.nx, el / D.nx));
   if (bad) atomicOr(d.flag, bit);
+}
+
+// Vertices of an isoparametric domain: its corner CG2 nodes.
+__global__ void __launch_bounds__(kElemBlock) k_corner_vertices(DevArrays d, int dom) {
+  const DomDev D = d.doms[dom];
+  double *VX = const_cast<double *>(d.vert) + 2 * (size_t)D.vert_off;
+  const double *XN = d.xnode + 2 * (size_t)D.node_off;
+  const int NX = 2 * D.nx + 1;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < D.nv; i += gridDim.x * blockDim.x) {
+    const int ix = i % (D.nx + 1), iy = i / (D.nx + 1);
+    const int j = 2 * iy * NX + 2 * ix;
+    VX[i] = XN[j];
+    VX[D.nv + i] = XN[D.nn + j];
+  }
 }
 
 inline unsigned grid_for(size_t n, unsigned block) {
@@ -142,6 +161,12 @@ hipError_t launch_check_finite_f(const float *p, size_t n, int *flag, int bit, h
   hipLaunchKernelGGL((k_check_finite<float>), dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, flag, bit);
   return hipGetLastError();
 }
+hipError_t launch_corner_vertices(const DevArrays &d, int dom, int nv, hipStream_t s) {
+  hipLaunchKernelGGL(k_corner_vertices, dim3(grid_for((size_t)nv, kElemBlock)), dim3(kElemBlock), 0,
+                     s, d, dom);
+  return hipGetLastError();
+}
+
 hipError_t launch_check_jacobian(const DevArrays &d, int n_s, int n_eblk, int bit, hipStream_t s) {
   if (n_s == 3)
     hipLaunchKernelGGL((k_check_jacobian<3>), dim3(n_eblk), dim3(kElemBlock), 0, s, d, bit);

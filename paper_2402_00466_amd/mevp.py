@@ -55,7 +55,8 @@ EXPORTS = ["mevp_default_params", "mevp_workspace_size", "mevp_create", "mevp_se
            "mevp_set_config", "mevp_get_config", "mevp_set_graph", "mevp_tune",
            "mevp_advect", "mevp_get_fields",
            "mevp_set_params",
-           "mevp_set_geometry", "mevp_set_fields", "mevp_set_forcing", "mevp_set_state",
+           "mevp_set_geometry", "mevp_set_geometry_cg2", "mevp_set_fields", "mevp_set_forcing",
+           "mevp_set_state",
            "mevp_step", "mevp_begin_step", "mevp_subcycles", "mevp_get_state", "mevp_sync",
            "mevp_check_inputs", "mevp_check_state", "mevp_timing_enable", "mevp_timing_read",
            "mevp_destroy", "mevp_status_string", "mevp_version"]
@@ -89,6 +90,7 @@ def lib():
     L.mevp_get_fields.argtypes = [vp, i, dp, dp]
     L.mevp_get_config.argtypes = [vp, C.POINTER(CConfig)]
     L.mevp_set_geometry.argtypes = [vp, i, dp]
+    L.mevp_set_geometry_cg2.argtypes = [vp, i, dp]
     L.mevp_set_fields.argtypes = [vp, i, dp, dp]
     L.mevp_set_forcing.argtypes = [vp, i, dp, dp]
     L.mevp_set_state.argtypes = [vp, i, dp, dp]
@@ -267,6 +269,12 @@ class Context:
         _check("mevp_set_geometry", lib().mevp_set_geometry(
             self._h, dom, self._arg(vertices, (2, d.nv), "vertices")))
 
+    def set_geometry_cg2(self, dom, nodes):
+        """Curved cells: CG2 node positions [2][(2nx+1)(2ny+1)] (isoparametric map)."""
+        d = self._dom(dom)
+        _check("mevp_set_geometry_cg2", lib().mevp_set_geometry_cg2(
+            self._h, dom, self._arg(nodes, (2, d.nn), "nodes")))
+
     def set_fields(self, dom, H, A):
         d = self._dom(dom)
         _check("mevp_set_fields", lib().mevp_set_fields(
@@ -352,6 +360,10 @@ class Context:
         torch = self._torch
         dev = self.device
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).contiguous().to(dev)
-        self.set_geometry(dom, t(inputs.vertices))
+        nodes = getattr(inputs, "nodes", None)
+        if nodes is not None:
+            self.set_geometry_cg2(dom, t(nodes))
+        else:
+            self.set_geometry(dom, t(inputs.vertices))
         self.set_fields(dom, t(inputs.H), t(inputs.A))
         self.set_forcing(dom, t(inputs.wind), t(inputs.ocean))

@@ -56,9 +56,17 @@ def gpu_run(domains, n_steps, n_sub, precision="fp64", states=None, params=None,
     return res
 
 
+def oracle_mesh(d):
+    """The oracle's mesh of a domain: isoparametric if it has CG2 node positions."""
+    import oracle
+    if getattr(d, "nodes", None) is not None:
+        return oracle.Mesh(d.nx, d.ny, d.n_s, d.n_a, nodes=d.nodes)
+    return oracle.Mesh(d.nx, d.ny, d.n_s, d.n_a, d.vertices)
+
+
 def oracle_run(d, n_steps, n_sub, state=None, params=None):
     import oracle
-    m = oracle.Mesh(d.nx, d.ny, d.n_s, d.n_a, d.vertices)
+    m = oracle_mesh(d)
     p = params or oracle.Params()
     v, S = (None, None) if state is None else state
     return m.run(p, d.H, d.A, d.wind, d.ocean, n_steps, n_sub, v=v, S=S)

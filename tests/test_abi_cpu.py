@@ -19,7 +19,7 @@ def M():
 def _declared_symbols():
     src = open(os.path.join(ROOT, "include", "mevp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mevp_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(mevp_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol(M):

@@ -77,7 +77,7 @@ def test_tune_keeps_state_and_result(M, tmp_path):
     assert np.array_equal(tuned[0], ref[0]) and np.array_equal(tuned[1], ref[1])
     # the cache answers without timing and names the same configuration
     lines = cache.read_text().split("\n")
-    assert lines[0].startswith("gfx950/fp64/ns6/na1/dom1/el2560/max64x40 ")
+    assert lines[0].startswith("gfx950/fp64/ns6/na1/dom1/el2560/max64x40/geo2560.0.0 ")
     ctx2 = _ctx(M, d)
     assert ctx2.tune(n_trial=5, cache_path=str(cache)) == (strategy, tuple(tile))
 
