@@ -99,20 +99,25 @@ def run_gpu(domains, precision, steps, warmup, n_sub, strategy=None, tile=None, 
     for k, d in enumerate(domains):
         ctx.upload(k, d)
     ctx.check_inputs()
-    # let the GPU clocks settle before tuning and timing (a short workload
-    # otherwise runs its first milliseconds at lower clocks): ~0.3 s of steps
-    # (the state they leave is the warm-up's starting point, like the tuner's)
-    t_settle = time.perf_counter()
-    while True:
-        ctx.step(n_sub)
-        ctx.sync()
-        if time.perf_counter() - t_settle > 0.3:
-            break
+    # let the GPU clocks settle before tuning and again before timing: a short
+    # workload otherwise runs its first milliseconds at lower clocks, and the
+    # tuner's host round trips of the state let them drop (measured: the first
+    # 10 steps after tuning ran ~5 % slow at 256 x 256). ~0.3 s of steps each;
+    # the state they leave is the warm-up's starting point.
+    def settle():
+        t_settle = time.perf_counter()
+        while True:
+            ctx.step(n_sub)
+            ctx.sync()
+            if time.perf_counter() - t_settle > 0.3:
+                break
+    settle()
     if strategy is None and tune:
         ctx.tune(n_trial=max(10, min(n_sub, 50)))
     elif strategy is not None:
         ctx.set_config(strategy, tile or (16, 14))
     config = ctx.get_config()
+    settle()
     for _ in range(warmup):
         ctx.step(n_sub)
     # start-of-step kernel alone (subtracted from the region to get the subcycle kernels)
