@@ -8,12 +8,16 @@ Prints ONE JSON line:
   value         element-subcycles per second (elements x subcycles x steps / time)
   roofline      the dominant kernel (the subcycle kernel of the tuned launch
                 configuration) against the HBM roofline: its algorithmic bytes
-                per launch over its average launch duration, i.e. the HIP-event
-                time of the timed region on the context's stream minus the
-                start-of-step kernels, divided by the number of launches
+                per launch (per-subcycle bytes x subcycles per launch) over its
+                average launch duration, i.e. the HIP-event time of the timed
+                region on the context's stream minus the start-of-step kernels
+                and any remainder launch, divided by the number of launches;
+                traffic = measured HBM bytes per launch from profiles/traffic.json
+                when recorded for the current kernel sources
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
-  variants      the same measurement for mixed precision, the larger meshes
-                and the 64-domain batch (one context, one launch per phase)
+  variants      the same measurement for mixed precision, other launch
+                strategies, the larger meshes, the 64-domain batch, general and
+                curved cells and n_s = 8
 
 The default workload is 256 x 256 cells (2 km on a 512 km square), 6 DG
 stress dofs, FP64, 100 subcycles per step, 10 steps.
@@ -32,7 +36,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 METRIC = "element-subcycles/sec (FP64 vs mixed/batched) + achieved HBM GB/s vs peak"
-KERNEL_SOURCES = ["paper_2402_00466_amd/csrc/mevp_kernels.hip",
+# every source file that holds device code (the traffic records are tied to a
+# hash of them)
+KERNEL_SOURCES = ["paper_2402_00466_amd/csrc/mevp_device.hpp",
+                  "paper_2402_00466_amd/csrc/mevp_kernels.hip",
+                  "paper_2402_00466_amd/csrc/mevp_kernels_ns3.hip",
+                  "paper_2402_00466_amd/csrc/mevp_kernels_ns6.hip",
+                  "paper_2402_00466_amd/csrc/mevp_kernels_ns8.hip",
                   "paper_2402_00466_amd/csrc/mevp_ref.hpp",
                   "paper_2402_00466_amd/csrc/mevp_internal.hpp"]
 

@@ -3,26 +3,33 @@
 // the per-n_s kernel translation units and mevp_kernels.hip).
 //
 // One subcycle (Table 1 of the paper: strain, stress, divergence, velocity)
-// is two launches:
-//   element phase  one element per lane: gather the 9 CG2 velocities, strain
-//                  rates, L2 projection onto the DG stress space, the VP stress
-//                  update of Listing 1 (S read and written once), the new
-//                  stress and the weak-form nodal forces of the element
-//                  (18 values, written to a scratch array, element-fastest).
-//                  Two kernels: parallelogram cells (constant Jacobian,
-//                  diagonal mass matrix, strain and divergence as exact
-//                  constant operators) and general bilinear cells (Jacobian
-//                  per Gauss point, local mass matrix factorised per element).
-//   node phase     one CG2 node per lane: sum the forces of the <= 4 elements
-//                  around the node in ascending element order (deterministic,
-//                  no atomics), then the lumped-mass velocity update.
-// The element maps are recomputed from the cell vertices in every subcycle
-// (the paper's "on-the-fly map", Sec. 3.2) instead of being stored.
+// has two parts:
+//   element update  one element per lane (element_compute): gather the 9 CG2
+//                   velocities, strain rates, L2 projection onto the DG
+//                   stress space, the VP stress update of Listing 1, the new
+//                   stress and the weak-form nodal forces of the element (18
+//                   values). Three cell geometries: parallelograms (constant
+//                   Jacobian, diagonal mass matrix, strain and divergence as
+//                   exact constant operators), bilinear cells and curved
+//                   isoparametric cells (Jacobian per Gauss point from the
+//                   cell map, local mass matrix factorised per element).
+//   node update     per CG2 node: sum the forces of the <= 4 elements around
+//                   it in ascending element order (deterministic, no atomics),
+//                   then the lumped-mass velocity update (update_nodes).
+// Kernels: k_fused runs both parts of one subcycle per tile with the forces
+// in LDS; k_fused_multi runs K = 2 or 3 subcycles per tile (temporal
+// blocking, recomputed halo); k_element + k_node run the parts as separate
+// launches with the forces in a scratch array; k_fused with persist = 1 runs
+// all subcycles of a call in one cooperative launch. All of them share the
+// element and node arithmetic, so their results agree bit for bit.
+// The cell maps are recomputed from the vertices (or CG2 node positions) in
+// every subcycle (the paper's "on-the-fly map", Sec. 3.2) instead of being
+// stored.
 //
 // Arrays are element- or node-fastest (structure of arrays), so consecutive
 // lanes touch consecutive addresses for S, H, A, the forces and the node
 // arrays; the 3x3 velocity gather of neighbouring elements overlaps and is
-// served from L2.
+// served from L2 (or LDS inside a tile).
 #include <hip/hip_cooperative_groups.h>
 
 #include "mevp_internal.hpp"
