@@ -83,6 +83,7 @@ KParams derive(const mevp_params &p) {
   k.Pstar = p.Pstar;
   k.C = p.C;
   k.dmin2 = p.DeltaMin * p.DeltaMin;
+  k.dmin2_16 = k.dmin2 / 16.0;
   if (p.relax_form == 1) {
     k.fac = p.alpha / (1.0 + p.alpha);
     k.ainv = 1.0 / (1.0 + p.alpha);

@@ -155,18 +155,24 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return fma(0.5 * y, e, y);
 }
 
-// VP stress at one Gauss point (Listing 1): Delta and P/Delta in double,
-// s11 = P/Delta (5/8 e11 + 3/8 e22) - P/2, s12 = P/Delta e12 / 4, s22 alike.
+// VP stress at one Gauss point (Listing 1) from the strain in the variables
+// A = (e11 + e22)/4, B = (e11 - e22)/8, Q = e12/4. The listing's
+//   Delta^2 = Delta_min^2 + 1.25 (e11^2 + e22^2) + 1.5 e11 e22 + e12^2
+// is 16 (A^2 + B^2 + Q^2) + Delta_min^2, so
+//   P/Delta = (P/4) / sqrt(A^2 + B^2 + Q^2 + Delta_min^2/16)   (in double),
+//   s11 = P/Delta (5/8 e11 + 3/8 e22) - P/2 = P/Delta (2A + B) - P/2,
+//   s22 = P/Delta (2A - B) - P/2,   s12 = P/Delta e12/4 = P/Delta Q.
 template <class T>
-__device__ __forceinline__ void vp_stress(const KParams &p, double P, T e11, T e12, T e22, T &s11,
+__device__ __forceinline__ void vp_stress(const KParams &p, double P, T A, T B, T Q, T &s11,
                                           T &s12, T &s22) {
-  const double de11 = e11, de12 = e12, de22 = e22;
-  const double D2 = p.dmin2 + 1.25 * (de11 * de11 + de22 * de22) + 1.5 * de11 * de22 + de12 * de12;
-  const double PD = P * rsqrt_nr(D2);  // D2 >= Delta_min^2, a normal double
+  const double dA = A, dB = B, dQ = Q;
+  const double inner = fma(dA, dA, fma(dB, dB, fma(dQ, dQ, p.dmin2_16)));
+  const double PD = (0.25 * P) * rsqrt_nr(inner);  // inner >= Delta_min^2/16, a normal double
   const T tPD = T(PD), thP = T(0.5 * P);
-  s11 = tPD * (T(0.625) * e11 + T(0.375) * e22) - thP;
-  s12 = tPD * T(0.25) * e12;
-  s22 = tPD * (T(0.625) * e22 + T(0.375) * e11) - thP;
+  const T A2 = T(2) * A;
+  s11 = tPD * (A2 + B) - thP;
+  s22 = tPD * (A2 - B) - thP;
+  s12 = tPD * Q;
 }
 
 // Velocities of the 9 local nodes of an element whose first node is j0 in
@@ -394,40 +400,48 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
   const T J00 = g.J00, J01 = g.J01, J10 = g.J10, J11 = g.J11;
   const T idet = T(1) / (J00 * J11 - J01 * J10);
 
-  // ---- strain ----
-  T E11[NS], E12[NS], E22[NS];
+  // ---- strain, projected, in the stress update's variables (vp_stress):
+  // EA = (E11 + E22)/4, EB = (E11 - E22)/8, EQ = E12/4 per coefficient, with
+  // E11 = (J11 Gxx - J10 Gxe)/|J|, E22 = (J00 Gye - J01 Gyx)/|J|,
+  // E12 = ((J00 Gxe - J01 Gxx) + (J11 Gyx - J10 Gye))/(2|J|), G = the
+  // reference operators applied to v and divided by the DG norm ----
+  const T s4 = T(0.25) * idet, s8 = T(0.125) * idet;
+  const T a00 = J00 * s4, a01 = J01 * s4, a10 = J10 * s4, a11 = J11 * s4;
+  const T b00 = J00 * s8, b01 = J01 * s8, b10 = J10 * s8, b11 = J11 * s8;
+  T EA[NS], EB[NS], EQ[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     T gxx = 0, gxe = 0, gyx = 0, gye = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       if (a_xi(k, a) != 0.0) {
-        gxx += T(a_xi(k, a)) * vx[a];
-        gyx += T(a_xi(k, a)) * vy[a];
+        const T c = T(a_xi(k, a) / dg_mass(k));
+        gxx += c * vx[a];
+        gyx += c * vy[a];
       }
       if (a_eta(k, a) != 0.0) {
-        gxe += T(a_eta(k, a)) * vx[a];
-        gye += T(a_eta(k, a)) * vy[a];
+        const T c = T(a_eta(k, a) / dg_mass(k));
+        gxe += c * vx[a];
+        gye += c * vy[a];
       }
     }
-    const T sc = idet * T(1.0 / dg_mass(k));
-    E11[k] = (J11 * gxx - J10 * gxe) * sc;
-    E22[k] = (J00 * gye - J01 * gyx) * sc;
-    E12[k] = T(0.5) * ((J00 * gxe - J01 * gxx) + (J11 * gyx - J10 * gye)) * sc;
+    // left to right: one multiply and three fused multiply-adds each
+    EA[k] = a11 * gxx - a10 * gxe + a00 * gye - a01 * gyx;
+    EB[k] = b11 * gxx - b10 * gxe - b00 * gye + b01 * gyx;
+    EQ[k] = b00 * gxe - b01 * gxx + b11 * gyx - b10 * gye;
   }
 
   // ---- stress update ----
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
-  const DgGauss<NS, Ngp<NS>::value, T> g11(E11), g12(E12), g22(E22);
+  const DgGauss<NS, Ngp<NS>::value, T> gA(EA), gB(EB), gQ(EQ);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
     const int i = q % Ngp<NS>::value, j = q / Ngp<NS>::value;
-    const T e11 = g11.at(i, j), e12 = g12.at(i, j), e22 = g22.at(i, j);
     const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
     T s11, s12, s22;
-    vp_stress<T>(p, P, e11, e12, e22, s11, s12, s22);
+    vp_stress<T>(p, P, gA.at(i, j), gB.at(i, j), gQ.at(i, j), s11, s12, s22);
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (Q::psi(k, q) != 0.0) {
@@ -525,19 +539,26 @@ __device__ __forceinline__ void element_general(const KParams &p, const Map &cel
   mass.solve(E11);
   mass.solve(E12);
   mass.solve(E22);
+  // the stress update's variables (vp_stress)
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const T a = T(0.25) * (E11[k] + E22[k]), b = T(0.125) * (E11[k] - E22[k]);
+    E11[k] = a;
+    E22[k] = b;
+    E12[k] = T(0.25) * E12[k];
+  }
 
   // ---- stress update ----
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
-  const DgGauss<NS, Ngp<NS>::value, T> g11(E11), g12(E12), g22(E22);
+  const DgGauss<NS, Ngp<NS>::value, T> gA(E11), gB(E22), gQ(E12);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
     const int i = q % Ngp<NS>::value, j = q / Ngp<NS>::value;
-    const T e11 = g11.at(i, j), e12 = g12.at(i, j), e22 = g22.at(i, j);
     const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
     T s11, s12, s22;
-    vp_stress<T>(p, P, e11, e12, e22, s11, s12, s22);
+    vp_stress<T>(p, P, gA.at(i, j), gB.at(i, j), gQ.at(i, j), s11, s12, s22);
     T J00, J01, J10, J11;
     cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
     const T wd = T(Q::w(q)) * (J00 * J11 - J01 * J10);

@@ -65,6 +65,7 @@ struct Launch {
 // Scalars the kernels need, derived once from mevp_params on the host.
 struct KParams {
   double Pstar, C, dmin2;  // P*, concentration factor, Delta_min^2
+  double dmin2_16;         // Delta_min^2 / 16
   double fac, ainv;        // stress relaxation weights
   double beta, inv_dt;     // velocity relaxation, 1/dt
   double rho_i, rhoCa, rhoCo, f_dt;  // densities x drag coefficients, Coriolis x dt
