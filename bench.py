@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")  # measured bytes per launch
 METRIC = "element-subcycles/sec (FP64 vs mixed/batched) + achieved HBM GB/s vs peak"
 # every source file that holds device code (the traffic records are tied to a
 # hash of them)
@@ -87,7 +88,7 @@ def alg_bytes(domains, precision):
 def load_traffic(workload, precision, strategy, tile):
     """HBM traffic per launch of the dominant kernel from committed rocprofv3
     PMC summaries, if they were taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = TRAFFIC_PATH
     if not os.path.exists(path):
         return None
     try:
@@ -269,7 +270,7 @@ def record_traffic(key, fetch_csv, write_csv, copy_mib, kernel_substr, command):
                      "copy_kib": sum(copies) / len(copies), "scale": factor}
     total = (out["fetch"]["kib_per_dispatch"] * out["fetch"]["scale"] +
              out["write"]["kib_per_dispatch"] * out["write"]["scale"]) * 1024.0
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = TRAFFIC_PATH
     db = json.load(open(path)) if os.path.exists(path) else {}
     db[key] = {"bytes_per_launch": total, "fetch": out["fetch"], "write": out["write"],
                "kernel": kernel_substr, "kernel_hash": kernel_hash(), "command": command}

@@ -1,0 +1,66 @@
+"""CPU checks of the benchmark script's contract parts that need no GPU: one
+GPU only, the algorithmic-byte model, and the traffic record built from two
+rocprofv3 PMC CSV files (scaled by the probe's device copy)."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_algorithmic_bytes_per_element_subcycle():
+    """The survey's per-unit model: 704.2 B per element-subcycle at 2048^2
+    FP64 n_s = 6 (S 288 B, H+A 16 B, vertices 16 B, nodes 96 B each), 560.2 B
+    mixed; 2.954 GB per subcycle."""
+    import bench
+    from synth_inputs import make_domain
+    d = make_domain(2048, 2048, 6, 1, seed=1)
+    tot64 = bench.alg_bytes([d], "fp64")[0]
+    totmx = bench.alg_bytes([d], "mixed")[0]
+    assert tot64 == 2048 * 2048 * (288 + 16) + 2049 ** 2 * 16 + 4097 ** 2 * 96
+    assert abs(tot64 / 2048 ** 2 - 704.2) < 0.1
+    assert abs(totmx / 2048 ** 2 - 560.2) < 0.1
+
+
+def _pmc_csv(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, val in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": "X", "Counter_Value": val})
+
+
+def test_traffic_record_scales_by_the_copy_calibration(tmp_path, monkeypatch):
+    import bench
+    monkeypatch.setattr(bench, "TRAFFIC_PATH", str(tmp_path / "traffic.json"))
+    kern = "void mevp::(anonymous namespace)::k_fused_multi<6, 1, double, double, 0, 17, 17, 3>(x)"
+    # 1 GiB copies read as 512 MiB by FETCH_SIZE (factor 2) and 1 GiB by WRITE_SIZE
+    _pmc_csv(tmp_path / "f.csv", [("__amd_rocclr_copyBuffer", 524288.0),
+                                  ("__amd_rocclr_copyBuffer", 524288.0),
+                                  ("__amd_rocclr_copyBuffer", 8.0), (kern, 1000.0), (kern, 1200.0)])
+    _pmc_csv(tmp_path / "w.csv", [("__amd_rocclr_copyBuffer", 1048576.0),
+                                  ("__amd_rocclr_copyBuffer", 1048576.0), (kern, 500.0),
+                                  (kern, 500.0)])
+    bench.record_traffic("w/fp64/fused_triple/16x16", str(tmp_path / "f.csv"),
+                         str(tmp_path / "w.csv"), 1024, "k_fused_multi<", "cmd")
+    rec = json.load(open(tmp_path / "traffic.json"))["w/fp64/fused_triple/16x16"]
+    assert rec["fetch"]["scale"] == pytest.approx(2.0) and rec["write"]["scale"] == pytest.approx(1.0)
+    assert rec["bytes_per_launch"] == pytest.approx((1100.0 * 2.0 + 500.0) * 1024.0)
+    assert rec["kernel_hash"] == bench.kernel_hash()
+    # a record is used only while the kernel sources are unchanged
+    assert bench.load_traffic("w", "fp64", "fused_triple", (16, 16)) == rec["bytes_per_launch"]
+    rec["kernel_hash"] = "stale"
+    json.dump({"w/fp64/fused_triple/16x16": rec}, open(tmp_path / "traffic.json", "w"))
+    assert bench.load_traffic("w", "fp64", "fused_triple", (16, 16)) is None
