@@ -32,6 +32,8 @@
 // served from L2 (or LDS inside a tile).
 #include <hip/hip_cooperative_groups.h>
 
+#include <type_traits>
+
 #include "mevp_internal.hpp"
 #include "mevp_ref.hpp"
 
@@ -72,31 +74,108 @@ __device__ __forceinline__ Cell<T> load_cell(const DomDev &D, const double *vert
   return c;
 }
 
+// Jacobian of a bilinear cell in the form its passes use: each entry is
+// affine in one reference coordinate, J00 = J00c + t tx, J10 = J10c + t ty,
+// J01 = J01c + s tx, J11 = J11c + s ty (s = xi - 1/2, t = eta - 1/2; centre
+// Jacobian and twist tx = (X3 - X2) - (X1 - X0), likewise ty), and the ξη terms
+// of |J| cancel, so |J| = c0 + c1 s + c2 t exactly.
+template <class T>
+struct BilinearJ {
+  static constexpr bool kLinearDet = true;
+  T J00c, J01c, J10c, J11c, tx, ty, c0, c1, c2;
+  __device__ __forceinline__ explicit BilinearJ(const Cell<T> &c) {
+    J00c = T(0.5) * (c.ax + c.bx);
+    J10c = T(0.5) * (c.ay + c.by);
+    J01c = T(0.5) * (c.cx + c.dx);
+    J11c = T(0.5) * (c.cy + c.dy);
+    tx = c.bx - c.ax;
+    ty = c.by - c.ay;
+    c0 = J00c * J11c - J01c * J10c;
+    c1 = J00c * ty - J10c * tx;
+    c2 = J11c * tx - J01c * ty;
+  }
+  __device__ __forceinline__ void jac(double xi, double eta, T &J00, T &J01, T &J10,
+                                      T &J11) const {
+    const double sv = xi - 0.5, tv = eta - 0.5;
+    J00 = J00c;
+    J10 = J10c;
+    J01 = J01c;
+    J11 = J11c;
+    if (tv != 0.0) {
+      J00 = J00c + T(tv) * tx;
+      J10 = J10c + T(tv) * ty;
+    }
+    if (sv != 0.0) {
+      J01 = J01c + T(sv) * tx;
+      J11 = J11c + T(sv) * ty;
+    }
+  }
+  // w |J| at (xi, eta)
+  __device__ __forceinline__ T wdet(double w, double xi, double eta) const {
+    const double sv = xi - 0.5, tv = eta - 0.5;
+    T r = T(w) * c0;
+    if (sv != 0.0) r += T(w * sv) * c1;
+    if (tv != 0.0) r += T(w * tv) * c2;
+    return r;
+  }
+};
+
 // Local mass matrix M_e = Psi W_e Psi^T (W_e = diag(w_q |J_q|)) factorised as
 // L D L^T with unit lower L; solve() applies M_e^-1 in place.
 template <int NS, class T>
 struct Ldl {
   T L[NS][NS];
   T invd[NS];
+  // sum_q w_q f_q psi_k(q) psi_l(q) with f = 1, s or t (which = 0, 1, 2)
+  template <class Q>
+  static constexpr double moment(int which, int k, int l) {
+    double r = 0.0;
+    for (int q = 0; q < Q::NG; ++q) {
+      const double f = which == 0 ? 1.0 : which == 1 ? Q::xi(q) - 0.5 : Q::eta(q) - 0.5;
+      r += Q::w(q) * f * Q::psi(k, q) * Q::psi(l, q);
+    }
+    return r;
+  }
   template <class Q, class Map>
   __device__ __forceinline__ void build(const Map &c) {
     T M[NS][NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k)
-#pragma unroll
-      for (int l = 0; l <= k; ++l) M[k][l] = T(0);
-#pragma unroll
-    for (int q = 0; q < Q::NG; ++q) {
-      T J00, J01, J10, J11;
-      c.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
-      const T wd = T(Q::w(q)) * (J00 * J11 - J01 * J10);
+    if constexpr (Map::kLinearDet) {
+      // |J| = c0 + c1 s + c2 t: M = c0 N + c1 S + c2 T with the quadrature's
+      // moments (exact: the rule integrates these polynomials exactly)
 #pragma unroll
       for (int k = 0; k < NS; ++k)
 #pragma unroll
         for (int l = 0; l <= k; ++l) {
-          const double pp = Q::psi(k, q) * Q::psi(l, q);
-          if (pp != 0.0) M[k][l] += T(pp) * wd;
+          T m = T(0);
+          bool have = false;
+          const double n0 = moment<Q>(0, k, l), n1 = moment<Q>(1, k, l), n2 = moment<Q>(2, k, l);
+          if (n0 != 0.0) {
+            m = T(n0) * c.c0;
+            have = true;
+          }
+          if (n1 != 0.0) {
+            m = have ? m + T(n1) * c.c1 : T(n1) * c.c1;
+            have = true;
+          }
+          if (n2 != 0.0) m = have ? m + T(n2) * c.c2 : T(n2) * c.c2;
+          M[k][l] = m;
         }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int l = 0; l <= k; ++l) M[k][l] = T(0);
+#pragma unroll
+      for (int q = 0; q < Q::NG; ++q) {
+        const T wd = c.wdet(Q::w(q), Q::xi(q), Q::eta(q));
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+#pragma unroll
+          for (int l = 0; l <= k; ++l) {
+            const double pp = Q::psi(k, q) * Q::psi(l, q);
+            if (pp != 0.0) M[k][l] += T(pp) * wd;
+          }
+      }
     }
     T dv[NS];
 #pragma unroll
@@ -212,7 +291,14 @@ __device__ __forceinline__ void load_velocity(const DomDev &D, const double *v, 
 // derivative tables as the velocity gradient.
 template <class T>
 struct Q2Map {
+  static constexpr bool kLinearDet = false;
   T x[9], y[9];
+  // w |J| at (xi, eta)
+  __device__ __forceinline__ T wdet(double w, double xi, double eta) const {
+    T J00, J01, J10, J11;
+    jac(xi, eta, J00, J01, J10, J11);
+    return T(w) * (J00 * J11 - J01 * J10);
+  }
   __device__ __forceinline__ void jac(double xi, double eta, T &J00, T &J01, T &J10,
                                       T &J11) const {
     J00 = J01 = J10 = J11 = T(0);
@@ -491,11 +577,34 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
 // per element. Same inputs and outputs as element_affine.
 // ---------------------------------------------------------------------------
 template <int NS, int NA, class T, class Map, class SOld>
+__device__ __forceinline__ void element_general_core(const KParams &p, const Map &cell,
+                                                     const double (&Hc)[NA],
+                                                     const double (&Ac)[NA], const T (&vx)[9],
+                                                     const T (&vy)[9], SOld sold, T (&R11)[NS],
+                                                     T (&R12)[NS], T (&R22)[NS], T (&fx)[9],
+                                                     T (&fy)[9]);
+
+template <int NS, int NA, class T, class Map, class SOld>
 __device__ __forceinline__ void element_general(const KParams &p, const Map &cell,
                                                 const double (&Hc)[NA], const double (&Ac)[NA],
                                                 const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                 T (&fx)[9], T (&fy)[9]) {
+  if constexpr (std::is_same<Map, Cell<T>>::value)
+    element_general_core<NS, NA, T>(p, BilinearJ<T>(cell), Hc, Ac, vx, vy, sold, R11, R12, R22,
+                                    fx, fy);
+  else
+    element_general_core<NS, NA, T>(p, cell, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+}
+
+// Map: BilinearJ or Q2Map (jac, wdet, and the mass-matrix build).
+template <int NS, int NA, class T, class Map, class SOld>
+__device__ __forceinline__ void element_general_core(const KParams &p, const Map &cell,
+                                                     const double (&Hc)[NA],
+                                                     const double (&Ac)[NA], const T (&vx)[9],
+                                                     const T (&vy)[9], SOld sold, T (&R11)[NS],
+                                                     T (&R12)[NS], T (&R22)[NS], T (&fx)[9],
+                                                     T (&fy)[9]) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
   Ldl<NS, T> mass;
@@ -559,9 +668,7 @@ __device__ __forceinline__ void element_general(const KParams &p, const Map &cel
     const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
     T s11, s12, s22;
     vp_stress<T>(p, P, gA.at(i, j), gB.at(i, j), gQ.at(i, j), s11, s12, s22);
-    T J00, J01, J10, J11;
-    cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
-    const T wd = T(Q::w(q)) * (J00 * J11 - J01 * J10);
+    const T wd = cell.wdet(Q::w(q), Q::xi(q), Q::eta(q));
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (Q::psi(k, q) != 0.0) {
