@@ -243,15 +243,20 @@ static void map_jacobian(const or_mesh *m, int e, double xi, double eta, double 
     J[3] = (1.0 - xi) * (Y[2] - Y[0]) + xi * (Y[3] - Y[1]);
     return;
   }
+  /* positions relative to the cell's local node 0: the derivatives of the
+   * CG2 basis sum to zero, so J is unchanged, and the sum no longer cancels
+   * absolute coordinates far larger than the cell */
+  int j0 = local_to_global(m, e, 0);
+  double x0 = m->nx_[j0], y0 = m->ny_[j0];
   J[0] = J[1] = J[2] = J[3] = 0.0;
   for (int a = 0; a < 9; ++a) {
     int j = local_to_global(m, e, a);
     double dx = dlag2(a % 3, xi) * lag2(a / 3, eta);
     double dy = lag2(a % 3, xi) * dlag2(a / 3, eta);
-    J[0] += m->nx_[j] * dx;
-    J[1] += m->nx_[j] * dy;
-    J[2] += m->ny_[j] * dx;
-    J[3] += m->ny_[j] * dy;
+    J[0] += (m->nx_[j] - x0) * dx;
+    J[1] += (m->nx_[j] - x0) * dy;
+    J[2] += (m->ny_[j] - y0) * dx;
+    J[3] += (m->ny_[j] - y0) * dy;
   }
 }
 

@@ -220,3 +220,19 @@ def test_iso_mesh_validation(oracle_mod):
         O.Mesh(4, 3, 6, 1, nodes=bad)
     with pytest.raises(ValueError):
         O.Mesh(4, 3, 6, 1)
+
+
+def test_iso_geometry_is_translation_invariant(oracle_mod):
+    """The cell geometry does not depend on where the mesh sits: the same curved
+    mesh of 64 m cells moved ~2000 km away gives the same w|J| and gradients.
+    Node positions are on a 2^-10 m grid, so the moved mesh is represented
+    exactly; a Jacobian summed from absolute positions would lose ~7 digits to
+    cancellation, one from positions relative to a cell node loses none."""
+    nodes = np.round(curved_nodes(6, 5, 64.0, 64.0, amp=0.15, seed=21) * 1024.0) / 1024.0
+    far = nodes + np.array([[2.0 ** 21], [-(2.0 ** 20)]])
+    assert np.array_equal(far - np.array([[2.0 ** 21], [-(2.0 ** 20)]]), nodes)
+    m0 = oracle_mod.Mesh(6, 5, 6, 1, nodes=nodes)
+    m1 = oracle_mod.Mesh(6, 5, 6, 1, nodes=far)
+    for e in (0, 13, 29):
+        for a, b in zip(m1.element_geometry(e), m0.element_geometry(e)):
+            assert rel(a, b) < 1e-14
