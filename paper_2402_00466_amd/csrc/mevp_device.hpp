@@ -318,12 +318,25 @@ struct Q2Map {
   }
 };
 
+// the 9 node positions of element (ex, ey) relative to its node 0, in both
+// precisions (the differences of nearby doubles are exact, and J then sums
+// cell-sized terms instead of cancelling absolute coordinates)
 template <class T>
 __device__ __forceinline__ Q2Map<T> load_q2map(const DomDev &D, const double *xnode, int ex,
                                                int ey) {
   const double *XN = xnode + 2 * (size_t)D.node_off;
+  const double *YN = XN + D.nn;
+  const int NX = 2 * D.nx + 1, j0 = 2 * ey * NX + 2 * ex;
+  const double x0 = XN[j0], y0 = YN[j0];
   Q2Map<T> m;
-  gather_velocity<T>(XN, XN + D.nn, 2 * ey * (2 * D.nx + 1) + 2 * ex, 2 * D.nx + 1, m.x, m.y);
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int j = j0 + b * NX + c;
+      m.x[3 * b + c] = T(XN[j] - x0);
+      m.y[3 * b + c] = T(YN[j] - y0);
+    }
   return m;
 }
 
