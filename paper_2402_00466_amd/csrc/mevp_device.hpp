@@ -15,7 +15,7 @@
 //                   cell map, local mass matrix factorised per element).
 //   node update     per CG2 node: sum the forces of the <= 4 elements around
 //                   it in ascending element order (deterministic, no atomics),
-//                   then the lumped-mass velocity update (update_nodes).
+//                   then the lumped-mass velocity update (NodeBatch).
 // Kernels: k_fused runs both parts of one subcycle per tile with the forces
 // in LDS; k_fused_multi runs K = 2 or 3 subcycles per tile (temporal
 // blocking, recomputed halo); k_element + k_node run the parts as separate
@@ -875,65 +875,87 @@ __global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p, Buf
 // order. uin(ix, iy, j, ux, uy) reads v^{p-1} of node j = iy * NX + ix,
 // out(ix, iy, j, vx, vy) stores v^p; boundary nodes get v = 0 (Dirichlet).
 // ---------------------------------------------------------------------------
-template <int R, int NT, int NF, int FW, class T, class UIn, class Out>
-__device__ __forceinline__ void update_nodes(const KParams &p, const DomDev &D, const double *nc,
-                                             int ix0, int ix1, int iy0, int iy1, int ex0, int ey0,
-                                             const T (*fl)[NF], UIn uin, Out out) {
-  const int tid = (int)threadIdx.x;
-  const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
-  const size_t nn = (size_t)D.nn;
-  const int w = ix1 - ix0, n = w * (iy1 - iy0);
-  // k / w via a float reciprocal: for k < 2^13 and w < 2^7 the product
-  // (k + 1/2) (1/w) is within 1e-3 of (k + 1/2) / w, which lies at least
-  // 1/(2w) from an integer, so the truncation is exact
-  static_assert(R * NT <= 8192, "node rounds beyond the exact float division");
-  const float rw = 1.0f / (float)w;
+template <int R, int NT>
+struct NodeBatch {
   int jn[R], ixs[R], iys[R];
   bool act[R], bnd[R];
   double ux[R], uy[R], o[R][6];
+
+  // index the nodes and issue all their loads (v^{p-1} through uin, the six
+  // node constants); nothing here reads the element forces, so a kernel may
+  // call it before the barrier that publishes them
+  template <class UIn>
+  __device__ __forceinline__ void load(const DomDev &D, const double *nc, int ix0, int ix1,
+                                       int iy0, int iy1, UIn uin) {
+    const int tid = (int)threadIdx.x;
+    const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
+    const size_t nn = (size_t)D.nn;
+    const int w = ix1 - ix0, n = w * (iy1 - iy0);
+    // k / w via a float reciprocal: for k < 2^13 and w < 2^7 the product
+    // (k + 1/2) (1/w) is within 1e-3 of (k + 1/2) / w, which lies at least
+    // 1/(2w) from an integer, so the truncation is exact
+    static_assert(R * NT <= 8192, "node rounds beyond the exact float division");
+    const float rw = 1.0f / (float)w;
 #pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const int k = tid + m * NT;
-    act[m] = k < n;
-    const int qy = act[m] ? (int)(((float)k + 0.5f) * rw) : 0;
-    ixs[m] = ix0 + (act[m] ? k - qy * w : 0);
-    iys[m] = iy0 + qy;
-    jn[m] = iys[m] * NX + ixs[m];
-    bnd[m] = ixs[m] == 0 || iys[m] == 0 || ixs[m] == NX - 1 || iys[m] == NY - 1;
-    if (act[m] && !bnd[m]) {
-      uin(ixs[m], iys[m], jn[m], ux[m], uy[m]);
+    for (int m = 0; m < R; ++m) {
+      const int k = tid + m * NT;
+      act[m] = k < n;
+      const int qy = act[m] ? (int)(((float)k + 0.5f) * rw) : 0;
+      ixs[m] = ix0 + (act[m] ? k - qy * w : 0);
+      iys[m] = iy0 + qy;
+      jn[m] = iys[m] * NX + ixs[m];
+      bnd[m] = ixs[m] == 0 || iys[m] == 0 || ixs[m] == NX - 1 || iys[m] == NY - 1;
+      if (act[m] && !bnd[m]) {
+        uin(ixs[m], iys[m], jn[m], ux[m], uy[m]);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) o[m][c] = nc[c * nn + jn[m]];
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < R; ++m) {
-    if (!act[m]) continue;
-    if (bnd[m]) {
-      out(ixs[m], iys[m], jn[m], 0.0, 0.0);
-      continue;
-    }
-    const int ix = ixs[m], iy = iys[m];
-    const int ney = (iy & 1) ? 1 : 2, nex = (ix & 1) ? 1 : 2;
-    const int ey_first = (iy & 1) ? (iy - 1) / 2 : iy / 2 - 1;
-    const int ex_first = (ix & 1) ? (ix - 1) / 2 : ix / 2 - 1;
-    const int b0 = (iy & 1) ? 1 : 2, c0 = (ix & 1) ? 1 : 2;
-    double Fx = 0.0, Fy = 0.0;
-    for (int tt = 0; tt < ney; ++tt) {
-      const int ly = ey_first + tt - ey0, bb = b0 - 2 * tt;
-      for (int ss = 0; ss < nex; ++ss) {
-        const int lx = ex_first + ss - ex0, c = c0 - 2 * ss;
-        const int a = 3 * bb + c, le = ly * FW + lx;
-        Fx += (double)fl[a][le];
-        Fy += (double)fl[9 + a][le];
+        for (int c = 0; c < 6; ++c) o[m][c] = nc[c * nn + jn[m]];
       }
     }
-    double vx, vy;
-    velocity_update6(p, o[m], ux[m], uy[m], Fx, Fy, vx, vy);
-    out(ix, iy, jn[m], vx, vy);
   }
-}
 
+  // sum the forces of the <= 4 elements around each node in ascending element
+  // order (element (ex, ey) at fl[.][(ey - ey0) * FW + ex - ex0]), update and
+  // store through out; boundary nodes get v = 0 (Dirichlet)
+  template <int NF, int FW, class T, class Out>
+  __device__ __forceinline__ void finish(const KParams &p, int ex0, int ey0, const T (*fl)[NF],
+                                         Out out) const {
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      if (!act[m]) continue;
+      if (bnd[m]) {
+        out(ixs[m], iys[m], jn[m], 0.0, 0.0);
+        continue;
+      }
+      const int ix = ixs[m], iy = iys[m];
+      const int ney = (iy & 1) ? 1 : 2, nex = (ix & 1) ? 1 : 2;
+      const int ey_first = (iy & 1) ? (iy - 1) / 2 : iy / 2 - 1;
+      const int ex_first = (ix & 1) ? (ix - 1) / 2 : ix / 2 - 1;
+      const int b0 = (iy & 1) ? 1 : 2, c0 = (ix & 1) ? 1 : 2;
+      double Fx = 0.0, Fy = 0.0;
+      for (int tt = 0; tt < ney; ++tt) {
+        const int ly = ey_first + tt - ey0, bb = b0 - 2 * tt;
+        for (int ss = 0; ss < nex; ++ss) {
+          const int lx = ex_first + ss - ex0, c = c0 - 2 * ss;
+          const int a = 3 * bb + c, le = ly * FW + lx;
+          Fx += (double)fl[a][le];
+          Fy += (double)fl[9 + a][le];
+        }
+      }
+      double vx, vy;
+      velocity_update6(p, o[m], ux[m], uy[m], Fx, Fy, vx, vy);
+      out(ix, iy, jn[m], vx, vy);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Node part of a tile: the velocity update of the CG2 nodes (ix, iy) in
+// [ix0, ix1) x [iy0, iy1) of one domain, row-major (consecutive lanes,
+// consecutive nodes), each lane taking up to R of them; NodeBatch::load may
+// run before the barrier that publishes the forces, NodeBatch::finish after.
+// uin(ix, iy, j, ux, uy) reads v^{p-1} of node j = iy * NX + ix,
+// out(ix, iy, j, vx, vy) stores v^p.
+// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Fused subcycle on one tile of EX x EY elements. The tile's first column
 // and row are a halo (the elements left of and below the owned
@@ -968,8 +990,7 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
       }
     }
   }
-  __syncthreads();
-  // ---- nodes owned by the tile ----
+  // ---- nodes owned by the tile: loads before the barrier, update after ----
   const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
   const size_t nn = (size_t)D.nn;
   const int ix0 = 2 * t.x0, iy0 = 2 * t.y0;
@@ -984,8 +1005,10 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
     B.v_out[j] = vx;
     B.v_out[nn + j] = vy;
   };
-  update_nodes<R, NT, NT, EX, T>(p, D, d.nc + (size_t)6 * D.node_off, ix0, ix1, iy0, iy1,
-                                 t.x0 - 1, t.y0 - 1, fl, uin, out);
+  NodeBatch<R, NT> nb;
+  nb.load(D, d.nc + (size_t)6 * D.node_off, ix0, ix1, iy0, iy1, uin);
+  __syncthreads();
+  nb.template finish<NT, EX, T>(p, t.x0 - 1, t.y0 - 1, fl, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1000,6 +1023,8 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
 //                  elements' stress stored at i = K-1);
 //   node phase     i < K-1: the nodes of the next element phase, velocity
 //                  update in place in LDS; i = K-1: the owned nodes, stored.
+// Each node phase's loads (v^{p-1}, node constants) are issued before the
+// barrier that publishes the forces when the registers allow (kEarly).
 // Every element and node update is the arithmetic of fused_tile, so a pass
 // equals K single subcycles bit for bit. Only v^{p-1} / S^{p-1} are read
 // and only v^{p+K-1} / S^{p+K-1} written (double buffering as in fused_tile).
@@ -1012,6 +1037,10 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
   constexpr int FX = EX + 2 * K - 2, FY = EY + 2 * K - 2, NT = FX * FY;  // lanes = elements
   // nodes of element phase 1, in LDS: [2 (x0-K+1), 2 (x0+TX+K-2)]
   constexpr int VW = 2 * TX + 4 * K - 5, VH = 2 * TY + 4 * K - 5;
+  // node loads before the barrier only where the registers allow it: up to 8
+  // waves per workgroup (2 per SIMD, 256 VGPRs); larger workgroups need 3
+  // waves per SIMD and would spill
+  constexpr bool kEarly = (NT + 63) / 64 <= 8;
   __shared__ T fl[18][NT];
   __shared__ double vl[2][VW * VH];
   const Tile t = tiles[blockIdx.x];
@@ -1065,8 +1094,8 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
         fl[9 + a][tid] = fy[a];
       }
     }
-    __syncthreads();
-    // ---- node phase i ----
+    // ---- node phase i: loads before the barrier, update after (kEarly) ----
+    if constexpr (!kEarly) __syncthreads();
     if (i < K - 1) {
       // nodes of element phase i+1: [2 (x0-K+i+1), 2 (x0+TX+K-2-i)]
       const int ix0 = max(2 * (ex0 + i + 1), 0), iy0 = max(2 * (ey0 + i + 1), 0);
@@ -1083,14 +1112,20 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
           ux = B.v_in[j];
           uy = B.v_in[nn + j];
         };
-        update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, ex0, ey0, fl, uin, out);
+        NodeBatch<R, NT> nb;
+        nb.load(D, nc, ix0, ix1, iy0, iy1, uin);
+        if constexpr (kEarly) __syncthreads();
+        nb.template finish<NT, FX, T>(p, ex0, ey0, fl, out);
       } else {
         auto uin = [&](int ix, int iy, int, double &ux, double &uy) {
           const int q = vlds(ix, iy);
           ux = vl[0][q];
           uy = vl[1][q];
         };
-        update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, ex0, ey0, fl, uin, out);
+        NodeBatch<R, NT> nb;
+        nb.load(D, nc, ix0, ix1, iy0, iy1, uin);
+        if constexpr (kEarly) __syncthreads();
+        nb.template finish<NT, FX, T>(p, ex0, ey0, fl, out);
       }
     } else {
       // the owned nodes, v to global memory
@@ -1107,7 +1142,10 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
         B.v_out[j] = vx;
         B.v_out[nn + j] = vy;
       };
-      update_nodes<R, NT, NT, FX, T>(p, D, nc, ix0, ix1, iy0, iy1, ex0, ey0, fl, uin, out);
+      NodeBatch<R, NT> nb;
+      nb.load(D, nc, ix0, ix1, iy0, iy1, uin);
+      if constexpr (kEarly) __syncthreads();
+      nb.template finish<NT, FX, T>(p, ex0, ey0, fl, out);
     }
     if (i < K - 1) __syncthreads();
   }
