@@ -188,7 +188,7 @@ def measure(domains, precision, steps, warmup, n_sub, workload, strategy=None, t
     tot, be, bn = alg_bytes(domains, precision)
     # launches of the subcycle kernel(s) in the timed region
     if strategy == "persistent":
-        launches, per_launch, kernel = steps, n_sub, "k_fused (persistent: all subcycles of a step)"
+        launches, per_launch, kernel = steps, n_sub, "k_fused_persist (all subcycles of a step)"
     elif strategy in DEPTH:
         depth = DEPTH[strategy]
         launches, per_launch = steps * (n_sub // depth), depth

@@ -19,8 +19,8 @@
 // Kernels: k_fused runs both parts of one subcycle per tile with the forces
 // in LDS; k_fused_multi runs K = 2 or 3 subcycles per tile (temporal
 // blocking, recomputed halo); k_element + k_node run the parts as separate
-// launches with the forces in a scratch array; k_fused with persist = 1 runs
-// all subcycles of a call in one cooperative launch. All of them share the
+// launches with the forces in a scratch array; k_fused_persist runs all
+// subcycles of a call in one cooperative launch. All of them share the
 // element and node arithmetic, so their results agree bit for bit.
 // The cell maps are recomputed from the vertices (or CG2 node positions) in
 // every subcycle (the paper's "on-the-fly map", Sec. 3.2) instead of being
@@ -620,8 +620,6 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
                                                      T (&fy)[9]) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
-  Ldl<NS, T> mass;
-  mass.template build<Q>(cell);
 
   // ---- strain ----
   T E11[NS], E12[NS], E22[NS];
@@ -658,6 +656,10 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
       }
     }
   }
+  // factorised only now: the velocities are dead, so the factor and the strain
+  // moments are the only large arrays live
+  Ldl<NS, T> mass;
+  mass.template build<Q>(cell);
   mass.solve(E11);
   mass.solve(E12);
   mass.solve(E22);
@@ -1151,23 +1153,28 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
   }
 }
 
-// Fused subcycle kernel. persist == 0: an ordinary launch, one tile per
-// workgroup, one subcycle (buffers b0). persist != 0: a cooperative launch
-// whose workgroups stay resident for n_sub subcycles; in subcycle i every
-// workgroup takes the tiles blockIdx.x, blockIdx.x + gridDim.x, ... (the grid
-// is a multiple of 8, so a workgroup stays on one XCD's band of the XCD-ordered
-// tile table), with buffers b0 for even i and b1 (= b0 swapped) for odd i,
-// and a grid-wide barrier between subcycles. Every workgroup runs the same
-// number of barriers, so the grid always drains.
+// Fused subcycle kernel: one tile per workgroup, one subcycle.
 template <int NS, int NA, class T, class TS, int GK, int EX, int EY>
 __global__ void __launch_bounds__(EX *EY) k_fused(DevArrays d, KParams p, const Tile *tiles,
-                                                   int ntiles, Bufs b0, Bufs b1, int n_sub,
-                                                   int persist) {
+                                                   Bufs b) {
   __shared__ T fl[18][EX * EY];
-  if (!persist) {
-    fused_tile<NS, NA, T, TS, GK, EX, EY>(d, p, tiles[blockIdx.x], b0, fl);
-    return;
-  }
+  fused_tile<NS, NA, T, TS, GK, EX, EY>(d, p, tiles[blockIdx.x], b, fl);
+}
+
+// Persistent form (cooperative launch): the workgroups stay resident for n_sub
+// subcycles; in subcycle i every workgroup takes the tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ... (the grid is a multiple of 8, so a workgroup
+// stays on one XCD's band of the XCD-ordered tile table), with buffers b0 for
+// even i and b1 (= b0 swapped) for odd i, and a grid-wide barrier between
+// subcycles. Every workgroup runs the same number of barriers, so the grid
+// always drains. A kernel of its own: the subcycle loop lets the compiler
+// keep loop-invariant constants in registers, which the single-tile kernel
+// should not pay for.
+template <int NS, int NA, class T, class TS, int GK, int EX, int EY>
+__global__ void __launch_bounds__(EX *EY) k_fused_persist(DevArrays d, KParams p,
+                                                           const Tile *tiles, int ntiles,
+                                                           Bufs b0, Bufs b1, int n_sub) {
+  __shared__ T fl[18][EX * EY];
   cooperative_groups::grid_group g = cooperative_groups::this_grid();
   for (int it = 0; it < n_sub; ++it) {
     const Bufs &b = (it & 1) ? b1 : b0;
@@ -1552,11 +1559,12 @@ inline hipError_t fused_one(const DevArrays &d, const KParams &p, const Tile *ti
     }
     return hipErrorInvalidValue;
   }
-  auto kern = k_fused<NS, NA, T, T, GK, EX, EY>;
   if (!f.persist) {
-    hipLaunchKernelGGL(kern, dim3(ntiles), dim3(EX * EY), 0, s, d, p, tiles, ntiles, f.b0, f.b1, 1, 0);
+    hipLaunchKernelGGL((k_fused<NS, NA, T, T, GK, EX, EY>), dim3(ntiles), dim3(EX * EY), 0, s, d,
+                       p, tiles, f.b0);
     return hipGetLastError();
   }
+  auto kern = k_fused_persist<NS, NA, T, T, GK, EX, EY>;
   int per_cu = 0, dev = 0, n_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, EX * EY, 0);
   if (e == hipSuccess) e = hipGetDevice(&dev);
@@ -1569,9 +1577,9 @@ inline hipError_t fused_one(const DevArrays &d, const KParams &p, const Tile *ti
   DevArrays dd = d;
   KParams pp = p;
   const Tile *tt = tiles;
-  int nt = ntiles, ns = f.n_sub, one = 1;
+  int nt = ntiles, ns = f.n_sub;
   Bufs b0 = f.b0, b1 = f.b1;
-  void *args[] = {&dd, &pp, &tt, &nt, &b0, &b1, &ns, &one};
+  void *args[] = {&dd, &pp, &tt, &nt, &b0, &b1, &ns};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid), dim3(EX * EY),
                                     args, 0, s);
 }
