@@ -929,20 +929,28 @@ struct NodeBatch {
         continue;
       }
       const int ix = ixs[m], iy = iys[m];
-      const int ney = (iy & 1) ? 1 : 2, nex = (ix & 1) ? 1 : 2;
-      const int ey_first = (iy & 1) ? (iy - 1) / 2 : iy / 2 - 1;
-      const int ex_first = (ix & 1) ? (ix - 1) / 2 : ix / 2 - 1;
-      const int b0 = (iy & 1) ? 1 : 2, c0 = (ix & 1) ? 1 : 2;
-      double Fx = 0.0, Fy = 0.0;
-      for (int tt = 0; tt < ney; ++tt) {
-        const int ly = ey_first + tt - ey0, bb = b0 - 2 * tt;
-        for (int ss = 0; ss < nex; ++ss) {
-          const int lx = ex_first + ss - ex0, c = c0 - 2 * ss;
-          const int a = 3 * bb + c, le = ly * FW + lx;
-          Fx += (double)fl[a][le];
-          Fy += (double)fl[9 + a][le];
-        }
-      }
+      // the elements around the node: one (odd ix and iy, the centre node),
+      // two (an edge node) or four (a vertex node), ((ix-1)/2, (iy-1)/2) the
+      // first of them; the node is local node a = 3 b + c of each, b = 1 or 2
+      // (odd or even iy) in the first row of elements and 0 in the second,
+      // likewise c. All reads are issued at once: a missing element's read
+      // stays inside fl (any row, le + FW + 1 < NF + FW) and its value is
+      // replaced by +0.0, so the sum, in ascending element order, is the one
+      // over the elements that exist.
+      const bool two_x = !(ix & 1), two_y = !(iy & 1);
+      const int b3 = two_y ? 6 : 3, c0 = two_x ? 2 : 1;
+      const T *f = &fl[0][0] + (((iy - 1) >> 1) - ey0) * FW + ((ix - 1) >> 1) - ex0;
+      const T x00 = f[(b3 + c0) * NF], x01 = f[b3 * NF + 1], x10 = f[c0 * NF + FW],
+              x11 = f[FW + 1];
+      const T y00 = f[(9 + b3 + c0) * NF], y01 = f[(9 + b3) * NF + 1],
+              y10 = f[(9 + c0) * NF + FW], y11 = f[9 * NF + FW + 1];
+      double Fx = 0.0 + (double)x00, Fy = 0.0 + (double)y00;
+      Fx += two_x ? (double)x01 : 0.0;
+      Fy += two_x ? (double)y01 : 0.0;
+      Fx += two_y ? (double)x10 : 0.0;
+      Fy += two_y ? (double)y10 : 0.0;
+      Fx += (two_x && two_y) ? (double)x11 : 0.0;
+      Fy += (two_x && two_y) ? (double)y11 : 0.0;
       double vx, vy;
       velocity_update6(p, o[m], ux[m], uy[m], Fx, Fy, vx, vy);
       out(ix, iy, jn[m], vx, vy);
@@ -950,14 +958,6 @@ struct NodeBatch {
   }
 };
 
-// ---------------------------------------------------------------------------
-// Node part of a tile: the velocity update of the CG2 nodes (ix, iy) in
-// [ix0, ix1) x [iy0, iy1) of one domain, row-major (consecutive lanes,
-// consecutive nodes), each lane taking up to R of them; NodeBatch::load may
-// run before the barrier that publishes the forces, NodeBatch::finish after.
-// uin(ix, iy, j, ux, uy) reads v^{p-1} of node j = iy * NX + ix,
-// out(ix, iy, j, vx, vy) stores v^p.
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Fused subcycle on one tile of EX x EY elements. The tile's first column
 // and row are a halo (the elements left of and below the owned
