@@ -1204,60 +1204,76 @@ __global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams 
   const int ix = j % NX, iy = j / NX;
   const size_t o = 2 * (size_t)D.node_off;
 
-  double MH = 0.0, mA = 0.0;
+  // The elements around node (ix, iy): candidates ((ix-1)/2 + s, (iy-1)/2 + t),
+  // s, t in {0, 1}, in ascending element order; the second column (row) exists
+  // only for an even ix (iy), and each must lie in the domain. All four are
+  // evaluated without branches, so their loads are issued together; a missing
+  // one is evaluated on a clamped element and added as +0.0, which leaves the
+  // sum, in ascending element order, equal to the one over the elements that
+  // exist.
   const size_t ne = (size_t)D.ne;
   const double *Hd = d.H + (size_t)NA * D.elem_off;
   const double *Ad = d.A + (size_t)NA * D.elem_off;
-  for (int t = 0; t < 2; ++t) {
-    // candidate element rows: iy odd -> (iy-1)/2 only; iy even -> iy/2-1 and iy/2
-    const int ey = (iy & 1) ? ((t == 0) ? (iy - 1) / 2 : -1) : iy / 2 - 1 + t;
-    if (ey < 0 || ey >= D.ny) continue;
-    const int b = iy - 2 * ey;
-    for (int s = 0; s < 2; ++s) {
-      const int ex = (ix & 1) ? ((s == 0) ? (ix - 1) / 2 : -1) : ix / 2 - 1 + s;
-      if (ex < 0 || ex >= D.nx) continue;
-      const int cc = ix - 2 * ex;
-      const int a = 3 * b + cc;
-      const size_t e = (size_t)ey * D.nx + ex;
-      double Hc[NA], Ac[NA];
+  constexpr int NGP = Ngp<NS>::value;
+  const int exf = (ix - 1) >> 1, eyf = (iy - 1) >> 1;
+  double sh[4], sa[4];
+  bool ok[4];
 #pragma unroll
-      for (int k = 0; k < NA; ++k) {
-        Hc[k] = Hd[k * ne + e];
-        Ac[k] = Ad[k * ne + e];
-      }
-      // int rho_i h phi_a and int a phi_a over the element, for its cell map
-      auto integrals = [&](const auto &cell) {
-        double sh = 0.0, sa = 0.0;
+  for (int m = 0; m < 4; ++m) {
+    const int s = m & 1, t = m >> 1;
+    const int ex = exf + s, ey = eyf + t;
+    ok[m] = (s == 0 || !(ix & 1)) && (t == 0 || !(iy & 1)) && ex >= 0 && ey >= 0 &&
+            ex < D.nx && ey < D.ny;
+    const int exc = min(max(ex, 0), D.nx - 1), eyc = min(max(ey, 0), D.ny - 1);
+    // local node (b, c) of the node in the element (clamped for a missing one)
+    const int bb = min(max(iy - 2 * eyc, 0), 2), cc = min(max(ix - 2 * exc, 0), 2);
+    const size_t e = (size_t)eyc * D.nx + exc;
+    double Hc[NA], Ac[NA];
 #pragma unroll
-        for (int q = 0; q < Q::NG; ++q) {
-          double J00, J01, J10, J11;
-          cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
-          const double wd = Q::w(q) * (J00 * J11 - J01 * J10);
-          double hs = 0.0, as = 0.0;
-#pragma unroll
-          for (int k = 0; k < NA; ++k) {
-            hs += Hc[k] * Q::psi(k, q);
-            as += Ac[k] * Q::psi(k, q);
-          }
-          const double h = fmax(0.0, hs), ac = fmin(1.0, fmax(0.0, as));
-          double phi = 0.0;
-          switch (a) {  // keep the table lookup a constant per branch
-#define MEVP_PHI_CASE(A_) case A_: phi = Q::phi(A_, q); break;
-            MEVP_PHI_CASE(0) MEVP_PHI_CASE(1) MEVP_PHI_CASE(2) MEVP_PHI_CASE(3) MEVP_PHI_CASE(4)
-            MEVP_PHI_CASE(5) MEVP_PHI_CASE(6) MEVP_PHI_CASE(7) MEVP_PHI_CASE(8)
-#undef MEVP_PHI_CASE
-          }
-          sh += wd * p.rho_i * h * phi;
-          sa += wd * ac * phi;
-        }
-        MH += sh;
-        mA += sa;
-      };
-      if (D.kind == kGeoIso)
-        integrals(load_q2map<double>(D, d.xnode, ex, ey));
-      else
-        integrals(load_cell<double>(D, d.vert, ex, ey));
+    for (int k = 0; k < NA; ++k) {
+      Hc[k] = Hd[k * ne + e];
+      Ac[k] = Ad[k * ne + e];
     }
+    // the node's CG2 basis function at the Gauss points: L_c(x_i) L_b(x_j)
+    double Lx[NGP], Ly[NGP];
+#pragma unroll
+    for (int i = 0; i < NGP; ++i) {
+      const double x = Gauss1D<NGP>::x[i];
+      Lx[i] = cc == 0 ? q2_1d(0, x) : (cc == 1 ? q2_1d(1, x) : q2_1d(2, x));
+      Ly[i] = bb == 0 ? q2_1d(0, x) : (bb == 1 ? q2_1d(1, x) : q2_1d(2, x));
+    }
+    // int rho_i h phi_a and int a phi_a over the element, for its cell map
+    auto integrals = [&](const auto &cell) {
+      double h_int = 0.0, a_int = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q::NG; ++q) {
+        double J00, J01, J10, J11;
+        cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+        const double wd = Q::w(q) * (J00 * J11 - J01 * J10);
+        double hs = 0.0, as = 0.0;
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          hs += Hc[k] * Q::psi(k, q);
+          as += Ac[k] * Q::psi(k, q);
+        }
+        const double h = fmax(0.0, hs), ac = fmin(1.0, fmax(0.0, as));
+        const double phi = Lx[q % NGP] * Ly[q / NGP];
+        h_int += wd * p.rho_i * h * phi;
+        a_int += wd * ac * phi;
+      }
+      sh[m] = h_int;
+      sa[m] = a_int;
+    };
+    if (D.kind == kGeoIso)
+      integrals(load_q2map<double>(D, d.xnode, exc, eyc));
+    else
+      integrals(load_cell<double>(D, d.vert, exc, eyc));
+  }
+  double MH = 0.0, mA = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    MH += ok[m] ? sh[m] : 0.0;
+    mA += ok[m] ? sa[m] : 0.0;
   }
   const double wx = d.wind[o + j], wy = d.wind[o + D.nn + j];
   const double sp = sqrt(wx * wx + wy * wy);
