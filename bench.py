@@ -48,10 +48,6 @@ KERNEL_SOURCES = ["paper_2402_00466_amd/csrc/mevp_device.hpp",
                   "paper_2402_00466_amd/csrc/mevp_internal.hpp"]
 
 
-# subcycles per launch of the multi-subcycle strategies
-DEPTH = {"fused_pair": 2, "fused_triple": 3}
-
-
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -128,6 +124,7 @@ def run_gpu(domains, precision, steps, warmup, n_sub, strategy=None, tile=None, 
     elif strategy is not None:
         ctx.set_config(strategy, tile or (16, 14))
     config = ctx.get_config()
+    depth = ctx.launch_depth()  # subcycles per launch after the cell-kind fallbacks
     settle()
     for _ in range(warmup):
         ctx.step(n_sub)
@@ -142,7 +139,7 @@ def run_gpu(domains, precision, steps, warmup, n_sub, strategy=None, tile=None, 
     begin_ms = ev[0].elapsed_time(ev[1]) / 3
     # the launch that ends a step when the subcycles per launch do not divide
     # n_sub (subtracted too, so the average is that of the dominant kernel alone)
-    rem = n_sub % DEPTH.get(config[0], 1)
+    rem = n_sub % depth if depth > 1 else 0
     rem_ms = 0.0
     if rem:
         ev[0].record(ctx.stream)
@@ -176,25 +173,26 @@ def run_gpu(domains, precision, steps, warmup, n_sub, strategy=None, tile=None, 
     ctx.close()
     del ctx
     torch.cuda.synchronize()
-    return ms, wall, begin_ms, rem_ms, tim, config, advect_ms
+    return ms, wall, begin_ms, rem_ms, tim, config, advect_ms, depth
 
 
 def measure(domains, precision, steps, warmup, n_sub, workload, strategy=None, tile=None):
-    ms, wall, begin_ms, rem_ms, tim, config, advect_ms = run_gpu(domains, precision, steps, warmup,
-                                                                 n_sub, strategy, tile)
+    ms, wall, begin_ms, rem_ms, tim, config, advect_ms, depth = run_gpu(
+        domains, precision, steps, warmup, n_sub, strategy, tile)
     strategy, tile = config
     el_sub = sum(d.nx * d.ny for d in domains) * n_sub * steps
     value = el_sub / (ms * 1e-3)
     tot, be, bn = alg_bytes(domains, precision)
     # launches of the subcycle kernel(s) in the timed region
-    if strategy == "persistent":
+    # (depth: what the library runs per launch for this configuration and these
+    # cells, e.g. one subcycle for fused_pair with curved cells)
+    if depth == 0:
         launches, per_launch, kernel = steps, n_sub, "k_fused_persist (all subcycles of a step)"
-    elif strategy in DEPTH:
-        depth = DEPTH[strategy]
-        launches, per_launch = steps * (n_sub // depth), depth
-        kernel = f"k_fused_multi (K = {depth} subcycles per launch)"
     elif strategy == "two_phase":
         launches, per_launch, kernel = steps * n_sub, 1, "k_element + k_node (two-phase subcycle)"
+    elif depth > 1:
+        launches, per_launch = steps * (n_sub // depth), depth
+        kernel = f"k_fused_multi (K = {depth} subcycles per launch)"
     else:
         launches, per_launch, kernel = steps * n_sub, 1, "k_fused (one subcycle)"
     # average launch duration of the dominant kernel: the timed region minus the

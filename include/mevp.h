@@ -162,6 +162,16 @@ mevp_status mevp_set_strategy(mevp_ctx *ctx, mevp_strategy strategy);
 mevp_status mevp_set_config(mevp_ctx *ctx, const mevp_config *config);
 mevp_status mevp_get_config(mevp_ctx *ctx, mevp_config *config);
 
+/* Subcycles one launch of the subcycle kernel runs under the current
+ * configuration and geometry (Eq. (si:mevp): each subcycle needs the previous
+ * one's velocity, so a launch covers whole subcycles): 1 for FUSED and
+ * TWO_PHASE; 2 or 3 for FUSED_PAIR / FUSED_TRIPLE, less where the cells do not
+ * allow it (a bilinear domain: at most 2; a curved domain: 1); 0 for
+ * PERSISTENT when it runs all subcycles of a call in one launch (every domain
+ * of one geometry kind), else 1. A call of n subcycles then takes n / depth
+ * launches plus one for the remainder. EINVAL if ctx or depth is NULL. */
+mevp_status mevp_get_launch_depth(mevp_ctx *ctx, int *depth);
+
 /* Replace the parameters (validated as in mevp_create). */
 mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params);
 

@@ -554,14 +554,42 @@ mevp_status mevp_begin_step(mevp_ctx *ctx) {
   return begin_step_on(ctx, ctx->stream);
 }
 
+// Subcycles per launch of the fused strategies: FUSED_PAIR / FUSED_TRIPLE run
+// 2 / 3, but three per launch exist for parallelogram cells only (with a
+// bilinear domain FUSED_TRIPLE runs two per launch) and with an isoparametric
+// domain both run one per launch.
+static int fused_depth(const mevp_ctx *ctx) {
+  const Launch &ts = ctx->tile_split;
+  int most = ctx->strategy == MEVP_STRATEGY_FUSED_TRIPLE ? 3
+             : ctx->strategy == MEVP_STRATEGY_FUSED_PAIR ? 2 : 1;
+  if (most == 3 && ts.n[kGeoBilinear] > 0) most = 2;
+  if (ts.n[kGeoIso] > 0) most = 1;
+  return most;
+}
+
+// The persistent strategy runs all subcycles of a call in one cooperative
+// launch when every tile takes the same kernel (one geometry kind).
+static bool persistent_whole(const mevp_ctx *ctx) {
+  int kinds = 0;
+  for (int k = 0; k < kNumGeo; ++k) kinds += ctx->tile_split.n[k] > 0;
+  return ctx->strategy == MEVP_STRATEGY_PERSISTENT && kinds == 1;
+}
+
+mevp_status mevp_get_launch_depth(mevp_ctx *ctx, int *depth) {
+  if (!ctx || !depth) return MEVP_EINVAL;
+  if (persistent_whole(ctx))
+    *depth = 0;
+  else if (ctx->strategy == MEVP_STRATEGY_TWO_PHASE || ctx->strategy == MEVP_STRATEGY_PERSISTENT)
+    *depth = 1;
+  else
+    *depth = fused_depth(ctx);
+  return MEVP_OK;
+}
+
 static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
   const bool mixed = ctx->prec == MEVP_MIXED;
   if (n == 0) return MEVP_OK;
-  // persistent: one cooperative launch for all n subcycles, when every tile
-  // takes the same kernel (all parallelogram domains, or none)
-  int kinds = 0;
-  for (int k = 0; k < kNumGeo; ++k) kinds += ctx->tile_split.n[k] > 0;
-  if (ctx->strategy == MEVP_STRATEGY_PERSISTENT && kinds == 1) {
+  if (persistent_whole(ctx)) {
     const int nxt = ctx->cur ^ 1;
     FusedArgs f;
     f.b0 = Bufs{v_buf(ctx, ctx->cur), v_buf(ctx, nxt), S_buf(ctx, ctx->cur), S_buf(ctx, nxt)};
@@ -584,16 +612,9 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
   for (int it = 0; it < n; ++it) {
     hipError_t e;
     if (ctx->strategy != MEVP_STRATEGY_TWO_PHASE) {
-      // FUSED_PAIR / FUSED_TRIPLE: 2 / 3 subcycles per launch while that many
-      // remain, then the rest in one launch
-      // (three per launch exist for parallelogram cells only: with a bilinear
-      // domain FUSED_TRIPLE runs two per launch; with an isoparametric domain
-      // both run one per launch)
-      const Launch &ts = ctx->tile_split;
-      int most = ctx->strategy == MEVP_STRATEGY_FUSED_TRIPLE ? 3
-                 : ctx->strategy == MEVP_STRATEGY_FUSED_PAIR ? 2 : 1;
-      if (most == 3 && ts.n[kGeoBilinear] > 0) most = 2;
-      if (ts.n[kGeoIso] > 0) most = 1;
+      // FUSED_PAIR / FUSED_TRIPLE: fused_depth subcycles per launch while that
+      // many remain, then the rest in one launch
+      const int most = fused_depth(ctx);
       const int depth = most < n - it ? most : n - it;
       const int nxt = ctx->cur ^ 1;
       FusedArgs f;

@@ -52,7 +52,7 @@ class CDomain(C.Structure):
 _lib = None
 
 EXPORTS = ["mevp_default_params", "mevp_workspace_size", "mevp_create", "mevp_set_strategy",
-           "mevp_set_config", "mevp_get_config", "mevp_set_graph", "mevp_tune",
+           "mevp_set_config", "mevp_get_config", "mevp_get_launch_depth", "mevp_set_graph", "mevp_tune",
            "mevp_advect", "mevp_get_fields",
            "mevp_set_params",
            "mevp_set_geometry", "mevp_set_geometry_cg2", "mevp_set_fields", "mevp_set_forcing",
@@ -89,6 +89,7 @@ def lib():
     L.mevp_advect.argtypes = [vp]
     L.mevp_get_fields.argtypes = [vp, i, dp, dp]
     L.mevp_get_config.argtypes = [vp, C.POINTER(CConfig)]
+    L.mevp_get_launch_depth.argtypes = [vp, C.POINTER(C.c_int)]
     L.mevp_set_geometry.argtypes = [vp, i, dp]
     L.mevp_set_geometry_cg2.argtypes = [vp, i, dp]
     L.mevp_set_fields.argtypes = [vp, i, dp, dp]
@@ -259,6 +260,13 @@ class Context:
         cfg = CConfig()
         _check("mevp_get_config", lib().mevp_get_config(self._h, C.byref(cfg)))
         return STRATEGY_NAMES[cfg.strategy], (cfg.tile_nx, cfg.tile_ny)
+
+    def launch_depth(self) -> int:
+        """Subcycles per launch of the current configuration (see mevp_get_launch_depth;
+        0: all subcycles of a call in one persistent launch)."""
+        k = C.c_int()
+        _check("mevp_get_launch_depth", lib().mevp_get_launch_depth(self._h, C.byref(k)))
+        return k.value
 
     def set_params(self, params: Params):
         _check("mevp_set_params", lib().mevp_set_params(self._h, C.byref(params.to_c())))

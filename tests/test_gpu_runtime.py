@@ -95,3 +95,35 @@ def test_timing_counts_launches(M):
     t = ctx.timing_read()
     assert t["element"][0] == 4 and t["node"][0] == 4
     ctx.timing_enable(0)
+
+
+@pytest.mark.parametrize("kind", ["parallelogram", "bilinear", "curved", "parallelogram+bilinear"])
+def test_launch_depth_matches_launches(M, kind):
+    """mevp_get_launch_depth reports what a call actually launches: 10 subcycles
+    take 10 / depth launches plus one for the remainder (one launch for the
+    persistent strategy when it runs the whole call)."""
+    d0 = make_domain(20, 18, 6, 1, seed=21, h=5e3,
+                     perturb=0.1 if kind == "bilinear" else 0.0,
+                     curved=0.1 if kind == "curved" else 0.0)
+    doms = [d0]
+    if kind == "parallelogram+bilinear":
+        doms.append(make_domain(15, 11, 6, 1, seed=22, h=5e3, perturb=0.1))
+    ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in doms])
+    for k, d in enumerate(doms):
+        ctx.upload(k, d)
+    most = {"parallelogram": 3, "bilinear": 2, "curved": 1, "parallelogram+bilinear": 2}[kind]
+    expect = {"fused": 1, "two_phase": 1, "fused_pair": min(2, most), "fused_triple": most,
+              "persistent": 1 if kind == "parallelogram+bilinear" else 0}
+    ctx.set_graph(False)
+    for strategy, depth in expect.items():
+        ctx.set_config(strategy, (16, 14))
+        assert ctx.launch_depth() == depth, strategy
+        ctx.timing_enable(64)
+        ctx.subcycles(10)
+        n_launch = ctx.timing_read()["element"][0]
+        ctx.timing_enable(0)
+        want = 1 if depth == 0 else 10 // depth + (1 if depth > 1 and 10 % depth else 0)
+        log(f"{kind} {strategy}: depth {depth}, {n_launch} launches for 10 subcycles")
+        assert n_launch == want, (strategy, n_launch, want)
+    ctx.sync()
+    ctx.close()
