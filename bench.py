@@ -37,13 +37,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")  # measured bytes per launch
 METRIC = "element-subcycles/sec (FP64 vs mixed/batched) + achieved HBM GB/s vs peak"
-# every source file that holds device code (the traffic records are tied to a
-# hash of them)
+# every source file that holds device code, and the build script with its
+# compiler flags (the traffic records are tied to a hash of them)
 KERNEL_SOURCES = ["paper_2402_00466_amd/csrc/mevp_device.hpp",
                   "paper_2402_00466_amd/csrc/mevp_kernels.hip",
                   "paper_2402_00466_amd/csrc/mevp_kernels_ns3.hip",
                   "paper_2402_00466_amd/csrc/mevp_kernels_ns6.hip",
                   "paper_2402_00466_amd/csrc/mevp_kernels_ns8.hip",
+                  "paper_2402_00466_amd/csrc/mevp_kernels_affine.hip",
+                  "paper_2402_00466_amd/csrc/mevp_kernels_affine_ns6_fp64.hip",
+                  "paper_2402_00466_amd/csrc/mevp_affine.hpp",
+                  "paper_2402_00466_amd/build.py",
                   "paper_2402_00466_amd/csrc/mevp_ref.hpp",
                   "paper_2402_00466_amd/csrc/mevp_internal.hpp"]
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libmevp.so")
 SOURCES = ["mevp_api.hip", "mevp_kernels.hip", "mevp_kernels_ns3.hip", "mevp_kernels_ns6.hip",
-           "mevp_kernels_ns8.hip"]
+           "mevp_kernels_ns8.hip", "mevp_kernels_affine.hip", "mevp_kernels_affine_ns6_fp64.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -26,6 +26,16 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
+
+
+# The FP64 parallelogram-cell fused kernels at n_s = 6 are scheduled for
+# memory clauses (the machine scheduler groups their loads): measured on one
+# MI355X against the default schedule, +1 % at 256 x 256, +1 % at 1024 x 1024
+# and +3 % at 2048 x 2048 (three subcycles per launch); the same schedule made
+# n_s = 8 3 % slower, mixed precision 1 % and the general-cell kernels up to
+# 4 %, so they keep the default.
+EXTRA_FLAGS = {"mevp_kernels_affine_ns6_fp64.hip": ["-mllvm",
+                                                    "-amdgpu-sched-strategy=max-memory-clause"]}
 
 
 def _includes():
@@ -41,7 +51,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmds.append([HIPCC] + FLAGS + _includes() + ["-c", "-o", obj, os.path.join(CSRC, src)])
+        cmds.append([HIPCC] + FLAGS + EXTRA_FLAGS.get(src, []) + _includes() +
+                    ["-c", "-o", obj, os.path.join(CSRC, src)])
     jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1), 16)
     procs, failed = [], []
     pending = list(cmds)

@@ -1605,8 +1605,7 @@ inline hipError_t fused_shape(const DevArrays &d, const KParams &p, const Launch
                               const FusedArgs &f, hipStream_t s) {
   hipError_t e = hipSuccess;
   const Tile *t = d.tiles;
-  if (L.n[kGeoAffine] > 0)
-    e = fused_one<NS, NA, T, kGeoAffine, EX, EY>(d, p, t, L.n[kGeoAffine], f, s);
+  if (L.n[kGeoAffine] > 0) e = fused_affine<NS, NA, T, EX, EY>(d, p, t, L.n[kGeoAffine], f, s);
   t += L.n[kGeoAffine];
   if (e == hipSuccess && L.n[kGeoBilinear] > 0)
     e = fused_one<NS, NA, T, kGeoBilinear, EX, EY>(d, p, t, L.n[kGeoBilinear], f, s);

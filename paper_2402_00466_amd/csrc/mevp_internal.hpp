@@ -118,6 +118,13 @@ hipError_t launch_advect_stage(const DevArrays &d, int n_a, int n_eblk, const do
                                const double *Ain, double *Hout, double *Aout, double dt, double ca,
                                double cb, hipStream_t s);
 hipError_t launch_fill(void *dst, size_t n_words32, uint32_t value, hipStream_t s);
+// Fused subcycle launch of the parallelogram-cell tiles of one tile shape
+// (defined in mevp_affine.hpp and instantiated, for every n_s, n_a, precision
+// and tile shape the dispatch reaches, in mevp_kernels_affine*.hip: units of
+// their own, so that each can be scheduled as measured best).
+template <int NS, int NA, class T, int EX, int EY>
+hipError_t fused_affine(const DevArrays &d, const KParams &p, const Tile *tiles, int ntiles,
+                        const FusedArgs &f, hipStream_t s);
 // per-n_s launchers (mevp_kernels_ns{3,6,8}.hip)
 hipError_t begin_step_ns3(const DevArrays &, const KParams &, int, const double *, int, hipStream_t);
 hipError_t begin_step_ns6(const DevArrays &, const KParams &, int, const double *, int, hipStream_t);
