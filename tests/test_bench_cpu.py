@@ -64,3 +64,34 @@ def test_traffic_record_scales_by_the_copy_calibration(tmp_path, monkeypatch):
     rec["kernel_hash"] = "stale"
     json.dump({"w/fp64/fused_triple/16x16": rec}, open(tmp_path / "traffic.json", "w"))
     assert bench.load_traffic("w", "fp64", "fused_triple", (16, 16)) is None
+
+
+@pytest.mark.parametrize("strategy,depth,launches,per_launch,kernel", [
+    ("fused_triple", 3, 33, 3, "k_fused_multi (K = 3"),
+    ("fused_triple", 2, 50, 2, "k_fused_multi (K = 2"),   # a bilinear domain present
+    ("fused_pair", 1, 100, 1, "k_fused (one subcycle)"),   # curved cells
+    ("fused", 1, 100, 1, "k_fused (one subcycle)"),
+    ("two_phase", 1, 100, 1, "k_element + k_node"),
+    ("persistent", 0, 1, 100, "k_fused_persist"),
+    ("persistent", 1, 100, 1, "k_fused (one subcycle)"),  # several cell kinds
+])
+def test_dominant_kernel_follows_the_reported_launch_depth(monkeypatch, strategy, depth,
+                                                           launches, per_launch, kernel):
+    """measure() counts the dominant kernel's launches from the subcycles per
+    launch the library reports (mevp_get_launch_depth), not from the strategy's
+    name: one step of 100 subcycles, 1 ms of timed region, no start-of-step or
+    remainder time."""
+    import bench
+    from synth_inputs import make_domain
+    d = make_domain(8, 8, 6, 1, seed=1)
+    tim = {"element": (launches, 1.0), "node": (0, 0.0)}
+    monkeypatch.setattr(bench, "run_gpu", lambda *a, **k: (
+        1.0, 0.01, 0.0, 0.0, tim, (strategy, (16, 14)), 0.0, depth))
+    r = bench.measure([d], "fp64", 1, 0, 100, "8x8", strategy, (16, 14))
+    rf = r["roofline"]
+    assert rf["kernel"].startswith(kernel)
+    assert rf["subcycles_per_launch"] == per_launch
+    assert r["kernels_ms"]["dominant_avg"] == pytest.approx(1.0 / launches)
+    tot = bench.alg_bytes([d], "fp64")[0]
+    # bytes per launch x launches / time: the method's bytes for the whole region
+    assert rf["achieved"] * 1e9 * 1e-3 == pytest.approx(tot * per_launch * launches)
