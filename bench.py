@@ -15,6 +15,8 @@ Prints ONE JSON line:
                 traffic = measured HBM bytes per launch from profiles/traffic.json
                 when recorded for the current kernel sources
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
+  advection     the DG advection of H and A (three Runge-Kutta stages), timed
+                outside the region: ms per step, algorithmic bytes, GB/s
   variants      the same measurement for mixed precision, other launch
                 strategies, the larger meshes, the 64-domain batch, general and
                 curved cells and n_s = 8
@@ -83,6 +85,22 @@ def alg_bytes(domains, precision):
         be += per_e + nn * 16
         bn += nn * 96
     return tot, be, bn
+
+
+def advect_bytes(domains):
+    """Algorithmic HBM bytes of one advection step of H and A (three SSP
+    Runge-Kutta stages, each a pass over the elements): per stage the stage's
+    input coefficients (2 n_a doubles per element) and, after the first stage,
+    the step's start values as well, the output coefficients, the CG2 velocity
+    (16 B per node) and the geometry (16 B per vertex). Neighbours' traces are
+    the same coefficients again and not counted twice."""
+    tot = 0
+    for d in domains:
+        ne, nn, nv = d.nx * d.ny, (2 * d.nx + 1) * (2 * d.ny + 1), (d.nx + 1) * (d.ny + 1)
+        u = ne * 2 * d.n_a * 8
+        for stage in range(3):
+            tot += u * (1 if stage == 0 else 2) + u + nn * 16 + nv * 16
+    return tot
 
 
 def load_traffic(workload, precision, strategy, tile):
@@ -204,6 +222,9 @@ def measure(domains, precision, steps, warmup, n_sub, workload, strategy=None, t
     kms = max(ms - steps * (begin_ms + rem_ms), 1e-9) / max(launches, 1)
     kbytes = tot * per_launch
     achieved = kbytes / (kms * 1e-3) / 1e9
+    # advection of H and A, timed outside the region (one call = one step)
+    ab = advect_bytes(domains)
+    ab_gbs = ab / (max(advect_ms, 1e-9) * 1e-3) / 1e9
     c0, t0 = tim["element"]
     c1, t1 = tim["node"]
     return {
@@ -214,6 +235,9 @@ def measure(domains, precision, steps, warmup, n_sub, workload, strategy=None, t
                        "diag_per_launch_events": {"subcycle_or_element_avg": t0 / max(c0, 1),
                                                   "node_avg": t1 / c1 if c1 else None,
                                                   "launches": c0}},
+        "advection": {"kernel": "k_advect (3 stages per step)", "ms_per_step": advect_ms,
+                      "alg_bytes_per_step": ab, "achieved_GBs": ab_gbs,
+                      "frac": ab_gbs / HBM_PEAK_GBS},
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": load_traffic(workload, precision, strategy, tile),
@@ -390,7 +414,8 @@ def main():
                 "elements": sum(d.nx * d.ny for d in ds), "config": r["config"],
                 "dominant_kernel_ms": r["kernels_ms"]["dominant_avg"],
                 "roofline_frac": r["roofline"]["frac"],
-                "achieved_GBs": r["roofline"]["achieved"]}
+                "achieved_GBs": r["roofline"]["achieved"],
+                "advection_frac": r["advection"]["frac"]}
             log(f"  {r['value']:.3e} element-subcycles/s ({r['config']['strategy']} "
                 f"{r['config']['tile']}), {r['roofline']['frac']:.3f} of HBM peak")
             del ds

@@ -95,3 +95,14 @@ def test_dominant_kernel_follows_the_reported_launch_depth(monkeypatch, strategy
     tot = bench.alg_bytes([d], "fp64")[0]
     # bytes per launch x launches / time: the method's bytes for the whole region
     assert rf["achieved"] * 1e9 * 1e-3 == pytest.approx(tot * per_launch * launches)
+
+
+def test_advection_bytes_per_step():
+    """Three stages: the first reads U^n, the others U^n and the stage input;
+    each writes its output and reads the CG2 velocity and the vertices once."""
+    import bench
+    from synth_inputs import make_domain
+    d = make_domain(8, 6, 6, 3, seed=1)
+    u = 8 * 6 * 2 * 3 * 8
+    per_stage_v_geo = 17 * 13 * 16 + 9 * 7 * 16
+    assert bench.advect_bytes([d]) == (u + u) + 2 * (2 * u + u) + 3 * per_stage_v_geo
