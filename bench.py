@@ -453,6 +453,7 @@ def main():
                    "n_sub": args.n_sub, "step": "one mEVP time step (start-of-step kernel + n_sub subcycles)"},
         "roofline": head["roofline"],
         "kernels_ms": head["kernels_ms"],
+        "advection": head["advection"],
         "cpu_baseline": cpu,
         "variants": variants,
         "kernel_hash": kernel_hash(),
