@@ -357,7 +357,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the mEVP subcycle "
-              "here is single-GPU; see the sharding notes in DESIGN.md", file=sys.stderr)
+              "here runs on a single GPU; a multi-GPU decomposition is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

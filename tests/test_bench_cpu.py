@@ -21,7 +21,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_algorithmic_bytes_per_element_subcycle():
-    """The survey's per-unit model: 704.2 B per element-subcycle at 2048^2
+    """The per-unit byte model: 704.2 B per element-subcycle at 2048^2
     FP64 n_s = 6 (S 288 B, H+A 16 B, vertices 16 B, nodes 96 B each), 560.2 B
     mixed; 2.954 GB per subcycle."""
     import bench
