@@ -124,7 +124,8 @@ typedef enum {
 } mevp_strategy;
 
 /* Launch configuration: strategy and the fused kernels' tile of owned
- * elements per workgroup (16 x 14; with n_a = 1 also 16 x 16 and 32 x 14). */
+ * elements per workgroup (16 x 14; with n_a = 1 also 16 x 16, 32 x 14 and
+ * 13 x 13). */
 typedef struct {
   int strategy;  /* a mevp_strategy */
   int tile_nx;

@@ -13,14 +13,15 @@ hipError_t fused_affine(const DevArrays &d, const KParams &p, const Tile *tiles,
   return fused_one<NS, NA, T, kGeoAffine, EX, EY>(d, p, tiles, ntiles, f, s);
 }
 
-static_assert(kTileShapes[0][0] == 17 && kTileShapes[0][1] == 15 && kTileShapes[1][0] == 17 &&
-                  kTileShapes[1][1] == 17 && kTileShapes[2][0] == 33 && kTileShapes[2][1] == 15,
+static_assert(kNumTileShapes == 4 && kTileShapes[0][0] == 17 && kTileShapes[0][1] == 15 &&
+                  kTileShapes[1][0] == 17 && kTileShapes[1][1] == 17 && kTileShapes[2][0] == 33 &&
+                  kTileShapes[2][1] == 15 && kTileShapes[3][0] == 14 && kTileShapes[3][1] == 14,
               "the instantiations follow kTileShapes");
 
 }  // namespace mevp
 
 // one instantiation; fused_t dispatches to tile shape 0 for every n_a and to
-// shapes 1 and 2 for n_a = 1
+// shapes 1 to 3 for n_a = 1
 #define MEVP_FA(NS_, NA_, T_, EX_, EY_)                                                   \
   template hipError_t fused_affine<NS_, NA_, T_, EX_, EY_>(const DevArrays &, const KParams &, \
                                                            const Tile *, int,               \
@@ -28,4 +29,4 @@ static_assert(kTileShapes[0][0] == 17 && kTileShapes[0][1] == 15 && kTileShapes[
 // every n_a and tile shape of one n_s and precision
 #define MEVP_FA_ALL(NS_, T_)                                                              \
   MEVP_FA(NS_, 1, T_, 17, 15) MEVP_FA(NS_, 3, T_, 17, 15) MEVP_FA(NS_, 6, T_, 17, 15)     \
-  MEVP_FA(NS_, 1, T_, 17, 17) MEVP_FA(NS_, 1, T_, 33, 15)
+  MEVP_FA(NS_, 1, T_, 17, 17) MEVP_FA(NS_, 1, T_, 33, 15) MEVP_FA(NS_, 1, T_, 14, 14)

@@ -1622,6 +1622,7 @@ inline hipError_t fused_t(const DevArrays &d, const KParams &p, const Launch &L,
   if constexpr (NA == 1) {  // the other tile shapes are built for one ice dof only
     if (f.shape == 1) return fused_shape<NS, NA, T, kTileShapes[1][0], kTileShapes[1][1]>(d, p, L, f, s);
     if (f.shape == 2) return fused_shape<NS, NA, T, kTileShapes[2][0], kTileShapes[2][1]>(d, p, L, f, s);
+    if (f.shape == 3) return fused_shape<NS, NA, T, kTileShapes[3][0], kTileShapes[3][1]>(d, p, L, f, s);
   }
   return hipErrorInvalidValue;
 }

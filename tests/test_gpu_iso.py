@@ -76,7 +76,7 @@ def test_iso_launch_configs_agree_bitwise(precision):
     ref = gpu_run([d], 2, 25, precision=precision, states=[state])[0]
     for strategy, tile in [("two_phase", None), ("fused", (16, 16)), ("fused", (32, 14)),
                            ("persistent", (16, 14)), ("fused_pair", (16, 14)),
-                           ("fused_triple", (16, 16))]:
+                           ("fused_triple", (16, 16)), ("fused_pair", (13, 13))]:
         got = gpu_run([d], 2, 25, precision=precision, states=[state], strategy=strategy,
                       tile=tile)[0]
         log(f"iso {strategy} {tile} vs fused (16, 14), {precision}")
