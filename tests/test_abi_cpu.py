@@ -137,3 +137,16 @@ def test_binding_fails_loudly_without_library(M, monkeypatch, tmp_path):
     monkeypatch.setattr(mm._build, "LIB", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         mm.lib()
+
+
+def test_binding_tiles_match_the_kernel_tile_shapes():
+    """The binding's owned-tile list is the kernels' tile table (workgroup tiles
+    including the one-element halo) minus the halo, in the same order."""
+    import re
+    import paper_2402_00466_amd.mevp as mevp
+    src = open(os.path.join(ROOT, "paper_2402_00466_amd", "csrc", "mevp_internal.hpp")).read()
+    m = re.search(r"kTileShapes\[kNumTileShapes\]\[2\] = \{(.*?)\};", src)
+    shapes = [(int(a) - 1, int(b) - 1) for a, b in re.findall(r"\{(\d+), (\d+)\}", m.group(1))]
+    n = int(re.search(r"kNumTileShapes = (\d+);", src).group(1))
+    assert len(shapes) == n
+    assert [tuple(t) for t in mevp.TILES] == shapes
