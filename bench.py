@@ -15,6 +15,7 @@ Prints ONE JSON line:
                 traffic = measured HBM bytes per launch from profiles/traffic.json
                 when recorded for the current kernel sources
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample
+  cpu_baseline_1thread  the same oracle on one host thread (one time step)
   advection     the DG advection of H and A (three Runge-Kutta stages), timed
                 outside the region: ms per step, algorithmic bytes, GB/s
   variants      the same measurement for mixed precision, other launch
@@ -326,6 +327,18 @@ def cpu_baseline(domains, n_sub, budget_s):
                       f"(n_s={d.n_s}), {el:.1f} s"}
 
 
+def cpu_baseline_1thread(domains, n_sub):
+    """The same oracle on one host thread: one time step of the first domain."""
+    import oracle
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        r = cpu_baseline(domains, n_sub, 0.0)
+    finally:
+        oracle.set_num_threads(threads)
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,10 +440,11 @@ def main():
             if a and b:
                 variants[f"{wl}/mixed_speedup_over_fp64"] = a["value"] / b["value"]
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(doms, args.n_sub, args.cpu_budget)
+        cpu1 = cpu_baseline_1thread(doms, args.n_sub)
 
     d0 = doms[0]
     line = {
@@ -455,6 +469,7 @@ def main():
         "kernels_ms": head["kernels_ms"],
         "advection": head["advection"],
         "cpu_baseline": cpu,
+        "cpu_baseline_1thread": cpu1,
         "variants": variants,
         "kernel_hash": kernel_hash(),
     }

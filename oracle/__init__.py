@@ -48,6 +48,7 @@ def lib():
         L.or_stress_gauss.argtypes = [C.c_void_p, C.c_void_p, dp, dp, dp, dp, dp, dp]
         L.or_project.argtypes = [C.c_void_p, dp, C.c_int, dp]
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
         L.or_advect.argtypes = [C.c_void_p, C.c_double, dp, dp, dp]
         L.or_advect_rate.argtypes = [C.c_void_p, dp, dp, dp]
         _lib = L
@@ -270,3 +271,8 @@ def tables(ns, na=1):
 
 def num_threads():
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int):
+    """Threads of the following oracle calls (results do not depend on it)."""
+    lib().or_set_num_threads(int(n))

@@ -90,6 +90,16 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Threads for the following calls (n >= 1). The results do not depend on it:
+ * every parallel loop writes disjoint outputs and sums in a fixed order. */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------------------
  * Reference element (R5-R7)
  * ------------------------------------------------------------------------- */

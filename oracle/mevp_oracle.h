@@ -107,6 +107,7 @@ void or_stress_gauss(const or_mesh *m, const or_params *p, const double *E, cons
 void or_project(const or_mesh *m, const double *g, int ncomp, double *coef);   /* [ncomp][nG][ne] -> [ncomp][ns][ne] */
 
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

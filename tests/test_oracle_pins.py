@@ -382,3 +382,21 @@ def test_projection_is_identity_on_dg_space_and_orthogonal(oracle_mod, ns):
     wdet = np.stack([m.element_geometry(e)[0] for e in range(m.ne)], axis=1)
     inner = np.einsum("kq,qe,cqe->cke", psiS, wdet, res)
     assert np.abs(inner).max() < 1e-12 * np.abs(np.einsum("kq,qe,cqe->cke", psiS, wdet, g)).max()
+
+
+def test_oracle_result_does_not_depend_on_its_thread_count():
+    """Every parallel loop of the oracle writes disjoint outputs and sums in a
+    fixed order, so one thread and all threads give the same bits."""
+    import oracle
+    from synth_inputs import make_domain
+    d = make_domain(16, 12, 6, 1, seed=8, h=10e3, perturb=0.1)
+    m = oracle.Mesh(d.nx, d.ny, d.n_s, d.n_a, d.vertices)
+    p = oracle.Params()
+    many = m.run(p, d.H, d.A, d.wind, d.ocean, 2, 10)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        one = m.run(p, d.H, d.A, d.wind, d.ocean, 2, 10)
+    finally:
+        oracle.set_num_threads(threads)
+    assert all(np.array_equal(a, b) for a, b in zip(many, one))
