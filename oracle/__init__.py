@@ -18,12 +18,19 @@ from . import build as _build
 _lib = None
 
 
+#: a different build of the oracle's source to load instead of the default one;
+#: set only by the mutation test, which plants mistakes in copies of the source
+#: and checks that the pins reject each of them
+ENV_LIB = "MEVP_ORACLE_LIB"
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get(ENV_LIB) or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.or_mesh_create.restype = C.c_void_p
         L.or_mesh_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, dp]

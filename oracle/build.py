@@ -14,15 +14,18 @@ LIB = os.path.join(HERE, "liboracle_mevp.so")
 SRC = os.path.join(HERE, "mevp_oracle.c")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-std=c99", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           "-o", LIB + ".tmp", SRC, "-lm"]
+FLAGS = ["-std=c99", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+         "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+
+
+def build(verbose: bool = False, src: str = SRC, lib: str = LIB, extra=()) -> str:
+    """Compile ``src`` (default: the oracle) to ``lib`` with the oracle's flags."""
+    cmd = ["gcc"] + FLAGS + list(extra) + ["-I", HERE, "-o", lib + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":
