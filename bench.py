@@ -22,8 +22,12 @@ Prints ONE JSON line:
                 strategies, the larger meshes, the 64-domain batch, general and
                 curved cells and n_s = 8
 
-The default workload is 256 x 256 cells (2 km on a 512 km square), 6 DG
-stress dofs, FP64, 100 subcycles per step, 10 steps.
+The default workload is the largest single-domain one: 2048 x 2048 cells
+(0.25 km on a 512 km square, 4.2M elements, 16.8M CG2 nodes, ~3 GB of state),
+6 DG stress dofs, FP64, 100 subcycles per step. Its state does not fit the
+256 MB Infinity Cache, so every launch streams from HBM. Variants whose
+working set does fit (256 x 256, 32 x 32) are labelled cache-resident and
+report their bound as latency/issue rather than HBM.
 """
 from __future__ import annotations
 
@@ -38,6 +42,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFS = 78.6           # MI355X FP64 vector (and matrix) peak
+MALL_BYTES = 256 << 20         # MI355X Infinity Cache (last-level, all XCDs)
+# FP64 operations of the parallelogram-cell element and node update per
+# element-subcycle at n_s = 6 (multiplies, adds and fused multiply-adds counted
+# as one operation each, from the arithmetic as written; flops = ops + FMAs)
+FP64_FLOP_PER_ELEMENT_SUBCYCLE = 1600.0
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")  # measured bytes per launch
 METRIC = "element-subcycles/sec (FP64 vs mixed/batched) + achieved HBM GB/s vs peak"
 # every source file that holds device code, and the build script with its
@@ -222,7 +232,6 @@ def measure(domains, precision, steps, warmup, n_sub, workload, strategy=None, t
     # start-of-step kernel and any remainder launch of each step
     kms = max(ms - steps * (begin_ms + rem_ms), 1e-9) / max(launches, 1)
     kbytes = tot * per_launch
-    achieved = kbytes / (kms * 1e-3) / 1e9
     # advection of H and A, timed outside the region (one call = one step)
     ab = advect_bytes(domains)
     ab_gbs = ab / (max(advect_ms, 1e-9) * 1e-3) / 1e9
@@ -239,11 +248,37 @@ def measure(domains, precision, steps, warmup, n_sub, workload, strategy=None, t
         "advection": {"kernel": "k_advect (3 stages per step)", "ms_per_step": advect_ms,
                       "alg_bytes_per_step": ab, "achieved_GBs": ab_gbs,
                       "frac": ab_gbs / HBM_PEAK_GBS},
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": load_traffic(workload, precision, strategy, tile),
-                     "alg_bytes_per_launch": kbytes, "subcycles_per_launch": per_launch},
+        "roofline": roofline(domains, precision, workload, strategy, tile, kernel, kbytes,
+                             kms, per_launch),
     }
+
+
+def roofline(domains, precision, workload, strategy, tile, kernel, kbytes, kms, per_launch):
+    """The dominant kernel against the HBM roofline. ``achieved`` is the
+    method's algorithmic bytes per launch over the launch's average duration
+    (the rate of a program that streams exactly the method's bytes). Beside
+    it: the bytes the kernel really moves (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    when recorded for the current sources) over the same time, and its useful
+    FP64 arithmetic rate against the FP64 peak. A working set that fits the
+    Infinity Cache is not bound by HBM: such workloads say so."""
+    achieved = kbytes / (kms * 1e-3) / 1e9
+    traffic = load_traffic(workload, precision, strategy, tile)
+    ws = working_set_bytes(domains, precision)
+    resident = ws <= MALL_BYTES
+    elems = sum(d.nx * d.ny for d in domains)
+    r = {"bound": "latency/issue (cache-resident)" if resident else "hbm",
+         "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+         "alg_bytes_per_launch": kbytes, "subcycles_per_launch": per_launch,
+         "working_set_bytes": ws, "achieved_is": "algorithmic bytes per launch / launch time"}
+    if traffic:
+        r["measured_GBs"] = traffic / (kms * 1e-3) / 1e9
+        r["measured_frac"] = r["measured_GBs"] / HBM_PEAK_GBS
+    if precision == "fp64" and workload.endswith("-dg2") and not workload.startswith("batch"):
+        tfs = FP64_FLOP_PER_ELEMENT_SUBCYCLE * elems * per_launch / (kms * 1e-3) / 1e12
+        r["fp64_TFs"] = tfs
+        r["fp64_frac"] = tfs / FP64_PEAK_TFS
+    return r
 
 
 def traffic_probe(workload, precision, strategy, tile, n_sub, copy_mib):
@@ -305,38 +340,52 @@ def record_traffic(key, fetch_csv, write_csv, copy_mib, kernel_substr, command):
     print(json.dumps({key: db[key]}))
 
 
-def cpu_baseline(domains, n_sub, budget_s):
-    """The FP64 oracle as it stands, on the host: whole time steps of the first
-    domain until ``budget_s`` of wall time is spent (at least one, at most 40)."""
+def oracle_mesh(d):
+    import oracle
+    return oracle.Mesh(d.nx, d.ny, d.n_s, d.n_a, d.vertices)
+
+
+def cpu_baseline(domains, n_sub, budget_s, chunk, m=None):
+    """The FP64 oracle as it stands, on the host, on a bounded sample of the
+    workload: the first domain, whole mesh, advanced from rest in calls of
+    ``chunk`` subcycles (each call a time step of that many subcycles: the
+    start-of-step work once, then the subcycles) until ``budget_s`` of wall
+    time is spent (at least one call, at most ``n_sub`` x 40 subcycles)."""
     import oracle
     d = domains[0]
-    m = oracle.Mesh(d.nx, d.ny, d.n_s, d.n_a, d.vertices)
+    m = m or oracle_mesh(d)
     p = oracle.Params()
     v = S = None
-    steps = 0
+    done = 0
     t0 = time.perf_counter()
     while True:
-        v, S = m.run(p, d.H, d.A, d.wind, d.ocean, 1, n_sub, v=v, S=S)
-        steps += 1
+        v, S = m.run(p, d.H, d.A, d.wind, d.ocean, 1, chunk, v=v, S=S)
+        done += chunk
         el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 40:
+        if el >= budget_s or done >= 40 * n_sub:
             break
-    return {"value": d.nx * d.ny * n_sub * steps / el, "unit": "element-subcycles/s",
+    return {"value": d.nx * d.ny * done / el, "unit": "element-subcycles/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{steps} time step(s) x {n_sub} subcycles of {d.nx}x{d.ny} "
-                      f"(n_s={d.n_s}), {el:.1f} s"}
+            "sample": f"{done // chunk} call(s) x {chunk} subcycles on the whole {d.nx}x{d.ny} "
+                      f"mesh (n_s={d.n_s}) from rest, {el:.1f} s"}
 
 
-def cpu_baseline_1thread(domains, n_sub):
-    """The same oracle on one host thread: one time step of the first domain."""
+def cpu_baseline_1thread(domains, n_sub, chunk, m=None):
+    """The same oracle on one host thread: one call of ``chunk`` subcycles."""
     import oracle
     threads = oracle.num_threads()
     oracle.set_num_threads(1)
     try:
-        r = cpu_baseline(domains, n_sub, 0.0)
+        r = cpu_baseline(domains, n_sub, 0.0, chunk, m)
     finally:
         oracle.set_num_threads(threads)
     return r
+
+
+def working_set_bytes(domains, precision):
+    """Device bytes the subcycle kernels touch (the context's workspace)."""
+    import paper_2402_00466_amd as M
+    return M.workspace_size([M.Domain(d.nx, d.ny, d.n_s, d.n_a) for d in domains], precision)
 
 
 def main():
@@ -345,7 +394,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-sub", type=int, default=100)
-    ap.add_argument("--workload", default="256x256-dg2")
+    ap.add_argument("--workload", default="2048x2048-dg2")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--strategy", default=None,
                     choices=["fused", "two_phase", "persistent", "fused_pair", "fused_triple"],
@@ -354,6 +403,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-chunk", type=int, default=10,
+                    help="subcycles per oracle call in the CPU baseline (a bounded sample)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the short counter-collection probe (see traffic_probe)")
     ap.add_argument("--copy-mib", type=int, default=1024)
@@ -401,22 +452,23 @@ def main():
     if not args.no_variants:
         other = "mixed" if args.precision == "fp64" else "fp64"
         plan = [(args.workload, other, args.steps, None, None),
-                (args.workload, args.precision, args.steps, "two_phase", None),
-                (args.workload, args.precision, args.steps, "fused", (16, 16)),
-                (args.workload, args.precision, args.steps, "fused_pair", (16, 16)),
-                (args.workload, args.precision, args.steps, "fused_triple", (16, 16)),
-                (args.workload, args.precision, 3, "persistent", (16, 14)),
+                (args.workload, args.precision, 3, "two_phase", None),
+                (args.workload, args.precision, 3, "fused", (16, 14)),
+                (args.workload, args.precision, 3, "fused_pair", (13, 13)),
+                ("256x256-dg2", "fp64", 10, None, None), ("256x256-dg2", "mixed", 10, None, None),
+                ("256x256-dg2", "fp64", 10, "two_phase", None),
+                ("256x256-dg2", "fp64", 10, "fused", (16, 16)),
+                ("256x256-dg2", "fp64", 3, "persistent", (16, 16)),
                 ("1024x1024-dg2", "fp64", 3, None, None), ("1024x1024-dg2", "mixed", 3, None, None),
-                ("2048x2048-dg2", "fp64", 3, None, None), ("2048x2048-dg2", "mixed", 3, None, None),
-                ("2048x2048-dg2", "fp64", 2, "two_phase", None),
-                ("2048x2048-dg2", "fp64", 2, "fused", (16, 14)),
-                ("2048x2048-dg2", "mixed", 2, "fused", (16, 14)),
                 ("batch64-dg2", "fp64", 2, None, None), ("batch64-dg2", "mixed", 2, None, None),
                 ("2048x2048-dg2-bilinear", "fp64", 2, None, None),
                 ("2048x2048-dg2-bilinear", "mixed", 2, None, None),
-                ("1024x1024-ns8", "fp64", 2, None, None),
+                ("1024x1024-ns8", "fp64", 2, None, None), ("1024x1024-ns8", "mixed", 2, None, None),
                 ("1024x1024-dg2-iso", "fp64", 2, None, None),
-                ("1024x1024-dg2-iso", "mixed", 2, None, None)]
+                ("1024x1024-dg2-iso", "mixed", 2, None, None),
+                ("32x32-dg1", "fp64", 10, None, None), ("32x32-dg1", "mixed", 10, None, None)]
+        plan = [x for x in plan if (x[0], x[1], x[3], x[4]) != (args.workload, args.precision,
+                                                                 None, None)]
         for wl, prec, st, strat, tl in plan:
             log(f"variant {wl} {prec} {strat or 'tuned'} {tl or ''} ({st} steps)")
             ds = doms if wl == args.workload else named_workload(wl)
@@ -426,16 +478,26 @@ def main():
                 "value": r["value"], "ms_per_step": r["ms_per_step"], "steps": st,
                 "elements": sum(d.nx * d.ny for d in ds), "config": r["config"],
                 "dominant_kernel_ms": r["kernels_ms"]["dominant_avg"],
+                "bound": r["roofline"]["bound"],
                 "roofline_frac": r["roofline"]["frac"],
                 "achieved_GBs": r["roofline"]["achieved"],
                 "advection_frac": r["advection"]["frac"]}
             log(f"  {r['value']:.3e} element-subcycles/s ({r['config']['strategy']} "
                 f"{r['config']['tile']}), {r['roofline']['frac']:.3f} of HBM peak")
             del ds
+        # the persistent kernel's grid-wide barrier: its per-step kernel time
+        # against the single-subcycle kernel's (same tiles, one tile per
+        # workgroup at 256 x 256) over the 99 barriers of a 100-subcycle step
+        per = variants.get("256x256-dg2/fp64/persistent/16x16")
+        one = variants.get("256x256-dg2/fp64/fused/16x16")
+        if per and one and args.n_sub > 1:
+            variants["persistent_barrier_us"] = 1e3 * (
+                per["dominant_kernel_ms"] - args.n_sub * one["dominant_kernel_ms"]) / (args.n_sub - 1)
         mix = variants.get(f"{args.workload}/mixed/tuned")
         if mix and args.precision == "fp64" and args.strategy is None:
             variants["mixed_speedup_over_fp64"] = mix["value"] / head["value"]
-        for wl in ("1024x1024-dg2", "2048x2048-dg2", "batch64-dg2"):
+        for wl in ("256x256-dg2", "1024x1024-dg2", "batch64-dg2", "2048x2048-dg2-bilinear",
+                   "1024x1024-ns8", "1024x1024-dg2-iso", "32x32-dg1"):
             a, b = variants.get(f"{wl}/mixed/tuned"), variants.get(f"{wl}/fp64/tuned")
             if a and b:
                 variants[f"{wl}/mixed_speedup_over_fp64"] = a["value"] / b["value"]
@@ -443,8 +505,10 @@ def main():
     cpu = cpu1 = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(doms, args.n_sub, args.cpu_budget)
-        cpu1 = cpu_baseline_1thread(doms, args.n_sub)
+        m = oracle_mesh(doms[0])
+        cpu = cpu_baseline(doms, args.n_sub, args.cpu_budget, args.cpu_chunk, m)
+        cpu1 = cpu_baseline_1thread(doms, args.n_sub, max(1, args.cpu_chunk // 5), m)
+        del m
 
     d0 = doms[0]
     line = {

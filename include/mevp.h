@@ -56,7 +56,8 @@ typedef enum {
   MEVP_ESTATE = -4,       /* call out of order, e.g. a step before geometry/fields/forcing are set */
   MEVP_ENONFINITE = -5,   /* non-finite or invalid values found by a check call */
   MEVP_EUNSUPPORTED = -6, /* the current device is not gfx950 */
-  MEVP_EINTERNAL = -7     /* a self-check failed (the tuner's bitwise comparison) */
+  MEVP_EINTERNAL = -7,    /* a self-check failed (the tuner's bitwise comparison) */
+  MEVP_EHOSTMEM = -8      /* host memory allocation failed (context, tables, tuner copies) */
 } mevp_status;
 
 typedef enum {
@@ -145,12 +146,22 @@ mevp_status mevp_default_params(mevp_params *out);
 mevp_status mevp_workspace_size(const mevp_domain_desc *domains, int n_domains,
                                 mevp_precision precision, size_t *bytes);
 
-/* Create a context. `workspace` is a caller-owned device buffer of at least
+/* Create a context: the device-resident counterpart of the arguments the
+ * appendix listing's stress update takes besides the fields (the VP
+ * parameters P*, Delta_min, the relaxation parameters alpha, beta, and the
+ * mesh the element loop runs over), for one or more domains. The paper's
+ * ports copy those buffers host <-> device around every kernel call
+ * (Sec. 3.2, Sec. 4); a context instead keeps them, the state and the forcing
+ * in the caller's workspace between calls.
+ * `workspace` is a caller-owned device buffer of at least
  * mevp_workspace_size bytes, 256-byte aligned, that must outlive the context.
  * `hip_stream` is a hipStream_t (NULL = default stream). Checks that the
  * current device is gfx950 (EUNSUPPORTED otherwise). Enqueues the zeroing of
- * the state (v = 0, S = 0) on the stream. On success *out owns host memory
- * released by mevp_destroy. */
+ * the state (v = 0, S = 0) on the stream and waits for it. On success *out
+ * owns host memory released by mevp_destroy (*out is NULL on any error).
+ * Errors: EINVAL (out, params, domains or workspace pointer/alignment),
+ * ENOMEM (ws_bytes below the required size), EDEVICE, EUNSUPPORTED,
+ * EHOSTMEM (the context's host tables could not be allocated). */
 mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
                         const mevp_domain_desc *domains, int n_domains, void *workspace,
                         size_t ws_bytes, void *hip_stream, mevp_ctx **out);
@@ -193,10 +204,31 @@ mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy);
  * FUSED_TRIPLE run one subcycle per launch. EINVAL on a bad domain or a NULL
  * pointer. */
 mevp_status mevp_set_geometry_cg2(mevp_ctx *ctx, int dom, const double *node_xy);
+/* Ice height H and concentration A of domain `dom`, [n_a][nx*ny] DG
+ * coefficients each: the H and A arguments of the appendix listing's stress
+ * update, clamped at the Gauss points there and in Listing 1 (h >= 0,
+ * 0 <= a <= 1) and advected by Eq. (si:ad). Stream-ordered copy (device or
+ * host pointers); EINVAL on a bad domain or a NULL pointer. Values are not
+ * checked here (mevp_check_inputs does). */
 mevp_status mevp_set_fields(mevp_ctx *ctx, int dom, const double *H, const double *A);
+/* Wind and ocean velocities of domain `dom` at the CG2 nodes,
+ * [2][(2nx+1)(2ny+1)] m/s each: they enter the external forcing F of
+ * Eq. (si:momentum), which the paper names as the combination of all external
+ * forcings without stating it; here F is quadratic air drag
+ * rho_a C_a |v_a| v_a weighted by the lumped concentration, and quadratic
+ * ocean drag rho_o C_o |v_o - v| (v_o - v) weighted likewise, its magnitude
+ * taken at the previous subcycle. Stream-ordered copy; EINVAL on a bad domain
+ * or a NULL pointer. */
 mevp_status mevp_set_forcing(mevp_ctx *ctx, int dom, const double *wind_xy,
                              const double *ocean_xy);
-/* State (v, S) of domain `dom`. In MEVP_MIXED, S is rounded to float. */
+/* State of domain `dom`: the CG2 velocity v [2][(2nx+1)(2ny+1)] of
+ * Eq. (si:momentum) and the DG stress S [3][n_s][nx*ny], the S11, S12, S22
+ * coefficients that the stress update of Listing 1 and the appendix listing
+ * reads and relaxes in place (Eq. (si:mevp) carries sigma^(p) from one
+ * subcycle to the next; the state also carries S from one step to the next).
+ * Stream-ordered copy into the current state buffers. In MEVP_MIXED, S is
+ * rounded to float on the device, so S must be a device pointer there
+ * (EINVAL otherwise). EINVAL on a bad domain or a NULL pointer. */
 mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const double *S);
 
 /* One time step of every domain (Sec. 2: momentum and mEVP subcycled inside
@@ -227,7 +259,9 @@ mevp_status mevp_subcycles(mevp_ctx *ctx, int n);
 
 /* Autotuner: pick the fastest launch configuration for this context's
  * domains. Runs mevp_begin_step on the current state, then times every
- * candidate (each strategy; each tile shape available for n_a) on
+ * candidate (FUSED, FUSED_PAIR and FUSED_TRIPLE with each tile shape available
+ * for n_a, and TWO_PHASE; not PERSISTENT, whose grid-wide barrier costs more
+ * than the gap between two launches of a replayed graph) on
  * n_trial >= 1 subcycles from that same state, restoring the state after each
  * trial, and checks that every candidate reproduces the first one bit for bit
  * (EINTERNAL if one does not; the previous configuration is kept). Leaves
@@ -235,7 +269,8 @@ mevp_status mevp_subcycles(mevp_ctx *ctx, int n);
  * cache_path (may be NULL): a text file of "key strategy tile_nx tile_ny"
  * lines, the key naming precision, n_s, n_a and the domain sizes; a matching
  * line is applied without timing, a new result is appended. Synchronous;
- * copies the state through host memory. */
+ * copies the state through host memory (EHOSTMEM if that cannot be
+ * allocated). */
 mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_config *chosen);
 
 /* Advect H and A of every domain over one step dt (Sec. 2: the advection
@@ -251,7 +286,12 @@ mevp_status mevp_advect(mevp_ctx *ctx);
 /* Copy out H and A of domain `dom` ([n_a][ne] each; either may be NULL). */
 mevp_status mevp_get_fields(mevp_ctx *ctx, int dom, double *H, double *A);
 
-/* Copy out the state of domain `dom` (either pointer may be NULL). */
+/* Copy out the state of domain `dom` in the layouts of mevp_set_state: the
+ * velocity v and the DG stress S after the last subcycle (Eq. (si:mevp);
+ * the in-out stress arguments of the appendix listing). Either pointer may be
+ * NULL. Stream-ordered: the values are valid once the stream has passed the
+ * call (mevp_sync). In MEVP_MIXED, S is widened from float on the device and
+ * must be a device pointer (EINVAL otherwise). EINVAL on a bad domain. */
 mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S);
 
 /* Wait for the context's stream; EDEVICE if any enqueued work failed. */

@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -182,7 +183,8 @@ mevp_status copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
 
 void timer_free(mevp_ctx *c) {
   for (auto &t : c->timer) {
-    for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : t.ev)
+      if (e) (void)hipEventDestroy(e);
     t.ev.clear();
     t.used = 0;
   }
@@ -249,6 +251,20 @@ void order_blocks(mevp_ctx *c) {
   }
 }
 
+// Host allocations (the context, its block tables, the tuner's state copies)
+// may fail; no exception crosses the C ABI: an exhausted host heap becomes
+// MEVP_EHOSTMEM and anything else thrown MEVP_EINTERNAL.
+template <class F>
+mevp_status host_guard(F &&f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return MEVP_EHOSTMEM;
+  } catch (...) {
+    return MEVP_EINTERNAL;
+  }
+}
+
 size_t s_words(const mevp_ctx *c) { return (size_t)3 * c->ns * c->tot_e; }
 size_t s_bytes(const mevp_ctx *c) {
   return (c->prec == MEVP_MIXED ? sizeof(float) : sizeof(double));
@@ -275,6 +291,7 @@ const char *mevp_status_string(mevp_status s) {
     case MEVP_ENONFINITE: return "non-finite or invalid values";
     case MEVP_EUNSUPPORTED: return "unsupported device";
     case MEVP_EINTERNAL: return "internal self-check failed";
+    case MEVP_EHOSTMEM: return "host memory allocation failed";
   }
   return "unknown status";
 }
@@ -307,9 +324,9 @@ mevp_status mevp_workspace_size(const mevp_domain_desc *domains, int n_domains,
   return MEVP_OK;
 }
 
-mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
-                        const mevp_domain_desc *domains, int n_domains, void *workspace,
-                        size_t ws_bytes, void *hip_stream, mevp_ctx **out) {
+static mevp_status create_impl(const mevp_params *params, mevp_precision precision,
+                               const mevp_domain_desc *domains, int n_domains, void *workspace,
+                               size_t ws_bytes, void *hip_stream, mevp_ctx **out) {
   if (!out) return MEVP_EINVAL;
   *out = nullptr;
   mevp_status st = validate_params(params);
@@ -326,8 +343,8 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MEVP_EDEVICE;
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MEVP_EUNSUPPORTED;
 
-  mevp_ctx *c = new (std::nothrow) mevp_ctx();
-  if (!c) return MEVP_EINVAL;
+  std::unique_ptr<mevp_ctx> owner(new mevp_ctx());
+  mevp_ctx *c = owner.get();
   c->device = dev;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->prec = precision;
@@ -398,12 +415,19 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
     rc = hip_status(launch_fill(base + L.flag, (L.total - L.flag) / 4, 0u, s));
   // the host vectors above must outlive the asynchronous copies
   if (rc == MEVP_OK) rc = hip_status(hipStreamSynchronize(s));
-  if (rc != MEVP_OK) {
-    delete c;
-    return rc;
-  }
-  *out = c;
+  if (rc != MEVP_OK) return rc;
+  *out = owner.release();
   return MEVP_OK;
+}
+
+mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
+                        const mevp_domain_desc *domains, int n_domains, void *workspace,
+                        size_t ws_bytes, void *hip_stream, mevp_ctx **out) {
+  if (out) *out = nullptr;
+  return host_guard([&] {
+    return create_impl(params, precision, domains, n_domains, workspace, ws_bytes, hip_stream,
+                       out);
+  });
 }
 
 mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params) {
@@ -422,8 +446,20 @@ static mevp_status set_kind(mevp_ctx *ctx, int dom, int kind) {
   if (ctx->dom_h[dom].kind == kind) return MEVP_OK;
   hipStream_t s = ctx->stream;
   graphs_clear(ctx);
+  const int old = ctx->dom_h[dom].kind;
   ctx->dom_h[dom].kind = kind;
-  order_blocks(ctx);
+  mevp_status ht = host_guard([&] {
+    order_blocks(ctx);
+    return MEVP_OK;
+  });
+  if (ht != MEVP_OK) {
+    ctx->dom_h[dom].kind = old;
+    (void)host_guard([&] {
+      order_blocks(ctx);  // the previous tables, same sizes as before
+      return MEVP_OK;
+    });
+    return ht;
+  }
   mevp_status st = copy(ctx->doms_d, ctx->dom_h.data(), sizeof(DomDev) * ctx->nd, s);
   if (st == MEVP_OK) st = copy(ctx->eblk_d, ctx->eblk_h.data(), sizeof(Blk) * ctx->eblk_h.size(), s);
   if (st == MEVP_OK) st = copy(ctx->tiles_d, ctx->tiles_h.data(), sizeof(Tile) * ctx->tiles_h.size(), s);
@@ -712,8 +748,20 @@ mevp_status mevp_set_config(mevp_ctx *ctx, const mevp_config *cfg) {
   ctx->strategy = static_cast<mevp_strategy>(cfg->strategy);
   graphs_clear(ctx);
   if (shape != ctx->shape) {
+    const int old = ctx->shape;
     ctx->shape = shape;
-    order_blocks(ctx);
+    mevp_status ht = host_guard([&] {
+      order_blocks(ctx);
+      return MEVP_OK;
+    });
+    if (ht != MEVP_OK) {
+      ctx->shape = old;
+      (void)host_guard([&] {
+        order_blocks(ctx);
+        return MEVP_OK;
+      });
+      return ht;
+    }
     mevp_status st = copy(ctx->tiles_d, ctx->tiles_h.data(), sizeof(Tile) * ctx->tiles_h.size(), ctx->stream);
     if (st == MEVP_OK) st = copy(ctx->eblk_d, ctx->eblk_h.data(), sizeof(Blk) * ctx->eblk_h.size(), ctx->stream);
     // the host tables must outlive the asynchronous copies
@@ -841,7 +889,14 @@ mevp_status mevp_timing_enable(mevp_ctx *ctx, int max_launches) {
   timer_free(ctx);
   if (st != MEVP_OK || max_launches == 0) return st;
   for (auto &t : ctx->timer) {
-    t.ev.resize(2 * (size_t)max_launches);
+    mevp_status ht = host_guard([&] {
+      t.ev.assign(2 * (size_t)max_launches, nullptr);
+      return MEVP_OK;
+    });
+    if (ht != MEVP_OK) {
+      timer_free(ctx);
+      return ht;
+    }
     for (auto &e : t.ev)
       if (hipEventCreate(&e) != hipSuccess) {
         timer_free(ctx);
@@ -926,7 +981,8 @@ static mevp_status restore_state(mevp_ctx *c, const std::vector<char> &buf) {
   return st;
 }
 
-mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_config *chosen) {
+static mevp_status tune_impl(mevp_ctx *ctx, int n_trial, const char *cache_path,
+                             mevp_config *chosen) {
   if (!ctx || n_trial < 1 || n_trial > 100000) return MEVP_EINVAL;
   if (!inputs_set(ctx)) return MEVP_ESTATE;
   const std::string key = tune_key(ctx);
@@ -946,7 +1002,10 @@ mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_c
           mevp_config{MEVP_STRATEGY_FUSED_TRIPLE, kTileShapes[sh][0] - 1, kTileShapes[sh][1] - 1});
   }
   cand.push_back(mevp_config{MEVP_STRATEGY_TWO_PHASE, kTileShapes[0][0] - 1, kTileShapes[0][1] - 1});
-  cand.push_back(mevp_config{MEVP_STRATEGY_PERSISTENT, kTileShapes[0][0] - 1, kTileShapes[0][1] - 1});
+  // PERSISTENT is not a candidate: its grid-wide barrier between subcycles
+  // costs several microseconds on MI355X, while consecutive launches of a
+  // replayed graph are a fraction of a microsecond apart, so it never wins
+  // (it stays available through mevp_set_config).
 
   mevp_config before;
   mevp_get_config(ctx, &before);
@@ -1005,6 +1064,10 @@ mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_c
     }
   }
   return MEVP_OK;
+}
+
+mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_config *chosen) {
+  return host_guard([&] { return tune_impl(ctx, n_trial, cache_path, chosen); });
 }
 
 void mevp_destroy(mevp_ctx *ctx) {

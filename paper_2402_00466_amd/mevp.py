@@ -24,7 +24,8 @@ TILES = [(16, 14), (16, 16), (32, 14), (13, 13)]
 _PREC = {"fp64": FP64, "f64": FP64, "mixed": MIXED}
 
 STATUS = {0: "MEVP_OK", -1: "MEVP_EINVAL", -2: "MEVP_ENOMEM", -3: "MEVP_EDEVICE",
-          -4: "MEVP_ESTATE", -5: "MEVP_ENONFINITE", -6: "MEVP_EUNSUPPORTED", -7: "MEVP_EINTERNAL"}
+          -4: "MEVP_ESTATE", -5: "MEVP_ENONFINITE", -6: "MEVP_EUNSUPPORTED", -7: "MEVP_EINTERNAL",
+          -8: "MEVP_EHOSTMEM"}
 
 
 class MevpError(RuntimeError):

@@ -125,10 +125,22 @@ def test_create_without_device_reports_device_error(M):
 def test_status_strings(M):
     L = M.lib()
     for s, text in [(0, "ok"), (-1, "invalid argument"), (-2, "workspace too small"),
-                    (-3, "device error"), (-4, "call out of order"), (-6, "unsupported device")]:
+                    (-3, "device error"), (-4, "call out of order"),
+                    (-5, "non-finite or invalid values"), (-6, "unsupported device"),
+                    (-7, "internal self-check failed"), (-8, "host memory allocation failed")]:
         assert L.mevp_status_string(s).decode() == text
     assert L.mevp_status_string(99).decode() == "unknown status"
     assert L.mevp_version().decode().startswith("mevp-gfx950")
+
+
+def test_binding_status_names_cover_the_header():
+    """Every status the header declares has a name in the binding."""
+    import re
+    import paper_2402_00466_amd.mevp as mevp
+    hdr = open(os.path.join(ROOT, "include", "mevp.h")).read()
+    body = re.search(r"typedef enum \{(.*?)\} mevp_status;", hdr, re.S).group(1)
+    declared = {int(v): k for k, v in re.findall(r"(MEVP_\w+) = (-?\d+)", body)}
+    assert declared == mevp.STATUS
 
 
 def test_binding_fails_loudly_without_library(M, monkeypatch, tmp_path):

@@ -92,11 +92,12 @@ def test_whole_run_mixed_small(strategy):
     _assert_close(field_errors(v, S, vr, Sr), TOLMIX, f"mixed 40x23 {strategy}")
 
 
-def _few_subcycles(name, n_sub, precision, tol, dom_index=0):
+def _few_subcycles(name, n_sub, precision, tol, dom_index=0, strategy="fused"):
     d = named_workload(name)[dom_index]
     state = random_state(d.nx, d.ny, d.n_s, seed=99)
-    log(f"workload {name} domain {dom_index} ({d.nx}x{d.ny}) {precision} {n_sub} subcycles from a seeded state")
-    (v, S), = gpu_run([d], 1, n_sub, precision=precision, states=[state])
+    log(f"workload {name} domain {dom_index} ({d.nx}x{d.ny}) {precision} {strategy} "
+        f"{n_sub} subcycles from a seeded state")
+    (v, S), = gpu_run([d], 1, n_sub, precision=precision, states=[state], strategy=strategy)
     vr, Sr = oracle_run(d, 1, n_sub, state=state)
     _assert_close(field_errors(v, S, vr, Sr), tol, f"{name} {precision} {n_sub} subcycles")
 
@@ -113,6 +114,16 @@ def test_few_subcycles_full_size_fp64(name):
 @pytest.mark.parametrize("name", FULL_SIZE)
 def test_few_subcycles_full_size_mixed(name):
     _few_subcycles(name, 3, "mixed", TOLMIX)
+
+
+@pytest.mark.parametrize("name", FULL_SIZE)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_few_subcycles_full_size_tuned(name, precision):
+    """The launch configuration the benchmark times (autotuned on the workload),
+    six subcycles (two or three launches of the multi-subcycle kernels, so the
+    state crosses memory between launches) against the oracle."""
+    _few_subcycles(name, 6, precision, TOL64 if precision == "fp64" else TOLMIX,
+                   strategy="tuned")
 
 
 def test_batched_equals_solo_bitwise_and_matches_oracle():
@@ -205,12 +216,13 @@ CONFIGS = [("two_phase", None), ("fused", (16, 16)), ("fused", (32, 14)),
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("perturb", [0.0, 0.1])
-def test_launch_configs_agree_bitwise(precision, perturb):
+@pytest.mark.parametrize("ns", [6, 8])
+def test_launch_configs_agree_bitwise(precision, perturb, ns):
     """Every launch strategy and tile shape sums the nodal forces in the same
     order from the same element computation: the results agree bitwise with
     the default (fused, 16 x 14 tiles), over tile boundaries and ragged tiles,
-    for parallelogram and general cells, over several steps."""
-    d = make_domain(173, 61, 6, 1, seed=61, h=2e3, perturb=perturb)
+    for parallelogram and general cells and n_s = 6 and 8, over several steps."""
+    d = make_domain(173, 61, ns, 1, seed=61, h=2e3, perturb=perturb)
     state = random_state(d.nx, d.ny, d.n_s, seed=5)
     ref = gpu_run([d], 2, 25, precision=precision, states=[state])[0]
     for strategy, tile in CONFIGS:
@@ -223,7 +235,8 @@ def test_launch_configs_agree_bitwise(precision, perturb):
 
 PAIR_FULL = [("256x256-dg2", "fp64"), ("256x256-dg2", "mixed"), ("2048x2048-dg2", "fp64"),
              ("2048x2048-dg2", "mixed"), ("2048x2048-dg2-bilinear", "fp64"),
-             ("batch64-dg2", "fp64"), ("batch64-dg2", "mixed")]
+             ("batch64-dg2", "fp64"), ("batch64-dg2", "mixed"),
+             ("1024x1024-ns8", "fp64"), ("1024x1024-ns8", "mixed")]
 
 
 @pytest.mark.parametrize("name,precision", PAIR_FULL)
