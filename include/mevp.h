@@ -313,6 +313,46 @@ mevp_status mevp_check_state(mevp_ctx *ctx);
 mevp_status mevp_timing_enable(mevp_ctx *ctx, int max_launches);
 mevp_status mevp_timing_read(mevp_ctx *ctx, int *count, double *total_ms);
 
+/* Bytes of the device array that mevp_step_static works in, per GPU. */
+#define MEVP_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate memory: code that must not call hipMalloc
+ * or create HIP objects, tight serving loops, harnesses that forbid
+ * allocation. One time step (mevp_begin_step, then n_subcycles >= 0 mEVP
+ * subcycles) of ONE domain with vertex geometry, without a context or a
+ * workspace: the values are those of mevp_create + mevp_set_geometry /
+ * _fields / _forcing / _state + mevp_step(n_subcycles) + mevp_get_state on
+ * the same inputs (bit for bit, in both precisions).
+ * Arguments: params and precision as in mevp_create; `domain` one descriptor;
+ * vertex_xy, H, A, wind_xy, ocean_xy the inputs in the layouts above, read in
+ * place by the kernels; v_xy [2][(2nx+1)(2ny+1)] and S [3][n_s][nx*ny] the
+ * state, read at the start and overwritten with the state after the step.
+ * Every array must be device memory on the current device (EINVAL
+ * otherwise), 8-byte aligned, of the stated size, and stay valid until the
+ * stream has passed the call. `hip_stream` as in mevp_create.
+ * Working memory: a file-scope device array of MEVP_STATIC_SCRATCH_BYTES, one
+ * per GPU, held from the library's first use on that GPU until the process
+ * ends; it takes the tables, both velocity and stress buffers and the node
+ * constants (at n_s = 6 about 610 bytes per element in FP64, 470 in mixed
+ * precision: up to ~1.1e5 / ~1.4e5 elements). ENOMEM if the domain needs more.
+ * The call allocates no device or host memory and creates no HIP object: no
+ * hipMalloc / hipFree, no graph, no event. It classifies the cells on the
+ * device as mevp_set_geometry does and waits for the stream once to read the
+ * result (so it cannot be captured into a graph); everything after that is
+ * stream-ordered and the outputs are valid once the stream has passed the
+ * call. Every call on a GPU shares that GPU's array, which keeps the last
+ * call's contents (this call clears what it uses first): calls that overlap
+ * on one GPU (other host threads, or other streams not ordered with this
+ * one) race and give wrong results; the caller serialises them.
+ * Errors: EINVAL (NULL or non-device pointer, bad params or descriptor,
+ * n_subcycles < 0), ENOMEM (the domain does not fit the array), EDEVICE,
+ * EUNSUPPORTED (not gfx950), EHOSTMEM. */
+mevp_status mevp_step_static(const mevp_params *params, mevp_precision precision,
+                             const mevp_domain_desc *domain, const double *vertex_xy,
+                             const double *H, const double *A, const double *wind_xy,
+                             const double *ocean_xy, double *v_xy, double *S, int n_subcycles,
+                             void *hip_stream);
+
 /* Release the context's host memory (the workspace stays the caller's).
  * Does not synchronise. NULL is a no-op. */
 void mevp_destroy(mevp_ctx *ctx);

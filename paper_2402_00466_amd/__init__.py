@@ -5,7 +5,9 @@
 device memory and streams.
 """
 from .mevp import (Context, Domain, MevpError, Params, default_params, lib, lib_path,
-                   workspace_size, EXPORTS, FP64, MIXED, STRATEGIES, TILES)
+                   step_static, workspace_size, EXPORTS, FP64, MIXED, STATIC_SCRATCH_BYTES,
+                   STRATEGIES, TILES)
 
 __all__ = ["Context", "Domain", "MevpError", "Params", "default_params", "lib", "lib_path",
-           "workspace_size", "EXPORTS", "FP64", "MIXED", "STRATEGIES", "TILES"]
+           "step_static", "workspace_size", "EXPORTS", "FP64", "MIXED", "STATIC_SCRATCH_BYTES",
+           "STRATEGIES", "TILES"]

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -28,6 +29,7 @@ struct mevp_ctx {
   std::vector<mevp_domain_desc> desc;
   std::vector<DomDev> dom_h;
   std::vector<Blk> eblk_h, nblk_h;
+  int n_nblk = 0;                     // node blocks (nblk_h.size(); kept apart for mevp_step_static)
   std::vector<Tile> tiles_h;
   Launch eblk_split{};                // element blocks grouped by geometry kind (GeoKind order)
   Launch tile_split{};                // tiles likewise
@@ -380,6 +382,7 @@ static mevp_status create_impl(const mevp_params *params, mevp_precision precisi
     c->dom_h.push_back(D);
     for (int f = 0; f < D.nn; f += kNodeBlock) c->nblk_h.push_back(Blk{i, f});
   }
+  c->n_nblk = (int)c->nblk_h.size();
   order_blocks(c);
 
   char *base = static_cast<char *>(workspace);
@@ -578,7 +581,7 @@ static bool inputs_set(const mevp_ctx *ctx) {
 static mevp_status begin_step_on(mevp_ctx *ctx, hipStream_t stream) {
   const int slot = timer_start(ctx, 2);
   mevp_status st = hip_status(launch_begin_step(ctx->d, ctx->kp, ctx->na, ctx->ns,
-                                                v_buf(ctx, ctx->cur), (int)ctx->nblk_h.size(),
+                                                v_buf(ctx, ctx->cur), ctx->n_nblk,
                                                 stream));
   timer_stop(ctx, 2, slot);
   return st;
@@ -675,7 +678,7 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
       timer_stop(ctx, 0, slot);
       if (e == hipSuccess) {
         slot = timer_start(ctx, 1);
-        e = launch_node_phase(ctx->d, ctx->kp, mixed, (int)ctx->nblk_h.size(), b, stream);
+        e = launch_node_phase(ctx->d, ctx->kp, mixed, ctx->n_nblk, b, stream);
         timer_stop(ctx, 1, slot);
       }
     }
@@ -1068,6 +1071,235 @@ static mevp_status tune_impl(mevp_ctx *ctx, int n_trial, const char *cache_path,
 
 mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_config *chosen) {
   return host_guard([&] { return tune_impl(ctx, n_trial, cache_path, chosen); });
+}
+
+// ---------------------------------------------------------------------------
+// mevp_step_static: one time step of one domain with no allocation
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+// The working memory of mevp_step_static: a file-scope device array, one copy
+// per GPU (each device that runs the library holds its own until the process
+// ends). Host code never passes the name `scratch` to a kernel or a copy: in
+// host code it is a stand-in, not a device address. The array's address on a
+// device is asked of HIP once, with that device current (scratch_base), and
+// only that address is used.
+__device__ __align__(256) unsigned char scratch[MEVP_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void *g_scratch_ptr[kMaxDevices];
+mevp_status g_scratch_status[kMaxDevices];
+
+// Device address of `scratch` on the current device `dev` (first call per
+// device: checks the architecture and looks the address up).
+mevp_status scratch_base(int dev, char **out) {
+  if (dev < 0 || dev >= kMaxDevices) return MEVP_EDEVICE;
+  std::call_once(g_scratch_once[dev], [dev] {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      g_scratch_status[dev] = MEVP_EDEVICE;
+      return;
+    }
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+      g_scratch_status[dev] = MEVP_EUNSUPPORTED;
+      return;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      g_scratch_status[dev] = MEVP_EDEVICE;
+      return;
+    }
+    g_scratch_ptr[dev] = ptr;
+    g_scratch_status[dev] = MEVP_OK;
+  });
+  *out = static_cast<char *>(g_scratch_ptr[dev]);
+  return g_scratch_status[dev];
+}
+
+// Layout of the scratch for one domain: the tables, the check flag, both v
+// buffers, the node constants and both S buffers (the inputs are read where
+// the caller keeps them).
+struct StaticLayout {
+  size_t doms, eblk, nblk, tiles, flag, v, nc, S, total;
+  int n_eblk, n_nblk, n_tiles;
+};
+
+mevp_status plan_static(const mevp_domain_desc *dd, mevp_precision prec, int shape,
+                        StaticLayout *L) {
+  Layout full;
+  mevp_status st = plan(dd, 1, prec, &full);  // validates the descriptor and precision
+  if (st != MEVP_OK) return st;
+  const size_t ws = (prec == MEVP_MIXED) ? sizeof(float) : sizeof(double);
+  const int tx = kTileShapes[shape][0] - 1, ty = kTileShapes[shape][1] - 1;
+  L->n_eblk = full.n_eblk;
+  L->n_nblk = full.n_nblk;
+  L->n_tiles = ((dd->nx + tx - 1) / tx) * ((dd->ny + ty - 1) / ty);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L->doms = take(sizeof(DomDev));
+  L->eblk = take(sizeof(Blk) * L->n_eblk);
+  L->nblk = take(sizeof(Blk) * L->n_nblk);
+  L->tiles = take(sizeof(Tile) * L->n_tiles);
+  L->flag = take(sizeof(int) * 4);
+  L->v = take(sizeof(double) * 4 * full.tot_n);
+  L->nc = take(sizeof(double) * 6 * full.tot_n);
+  L->S = take(ws * 6 * full.ns * full.tot_e);
+  L->total = off;
+  return MEVP_OK;
+}
+
+bool device_pointer(const void *p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice;
+}
+
+mevp_status step_static_impl(const mevp_params *params, mevp_precision precision,
+                             const mevp_domain_desc *domain, const double *vertex_xy,
+                             const double *H, const double *A, const double *wind_xy,
+                             const double *ocean_xy, double *v_xy, double *S, int n_subcycles,
+                             void *hip_stream) {
+  mevp_status st = validate_params(params);
+  if (st != MEVP_OK) return st;
+  if (!domain || !vertex_xy || !H || !A || !wind_xy || !ocean_xy || !v_xy || !S ||
+      n_subcycles < 0)
+    return MEVP_EINVAL;
+  // three subcycles per launch on 16 x 16 tiles (two on general cells); with
+  // n_a != 1 two per launch on 16 x 14 tiles (the kernels that exist there)
+  const int shape = domain->n_a == 1 ? 1 : 0;
+  StaticLayout L;
+  st = plan_static(domain, precision, shape, &L);
+  if (st != MEVP_OK) return st;
+  if (L.total > MEVP_STATIC_SCRATCH_BYTES) return MEVP_ENOMEM;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MEVP_EDEVICE;
+  char *base = nullptr;
+  st = scratch_base(dev, &base);
+  if (st != MEVP_OK) return st;
+  // the kernels read the inputs where they are: they must be device memory
+  const void *ptrs[] = {vertex_xy, H, A, wind_xy, ocean_xy, v_xy, S};
+  for (const void *p : ptrs)
+    if (!device_pointer(p) || reinterpret_cast<uintptr_t>(p) % sizeof(double) != 0)
+      return MEVP_EINVAL;
+
+  const mevp_domain_desc &dd = *domain;
+  DomDev D;
+  D.nx = dd.nx;
+  D.ny = dd.ny;
+  D.ne = dd.nx * dd.ny;
+  D.nn = (2 * dd.nx + 1) * (2 * dd.ny + 1);
+  D.nv = (dd.nx + 1) * (dd.ny + 1);
+  D.elem_off = D.node_off = D.vert_off = 0;
+  D.kind = kGeoBilinear;  // until the cells are classified
+
+  // a context on the stack, with no host tables: its vectors stay empty and
+  // nothing in it owns memory
+  mevp_ctx c;
+  c.device = dev;
+  c.stream = static_cast<hipStream_t>(hip_stream);
+  c.prec = precision;
+  c.params = *params;
+  c.kp = derive(*params);
+  c.nd = 1;
+  c.ns = dd.n_s;
+  c.na = dd.n_a;
+  c.tot_e = (size_t)D.ne;
+  c.tot_n = (size_t)D.nn;
+  c.tot_v = (size_t)D.nv;
+  c.n_nblk = L.n_nblk;
+  c.strategy = dd.n_a == 1 ? MEVP_STRATEGY_FUSED_TRIPLE : MEVP_STRATEGY_FUSED_PAIR;
+  c.shape = shape;
+  c.use_graph = false;
+  DevArrays &d = c.d;
+  DomDev *doms = reinterpret_cast<DomDev *>(base + L.doms);
+  Blk *eblk = reinterpret_cast<Blk *>(base + L.eblk);
+  Blk *nblk = reinterpret_cast<Blk *>(base + L.nblk);
+  Tile *tiles = reinterpret_cast<Tile *>(base + L.tiles);
+  d.doms = doms;
+  d.eblk = eblk;
+  d.nblk = nblk;
+  d.tiles = tiles;
+  d.flag = reinterpret_cast<int *>(base + L.flag);
+  d.vert = vertex_xy;
+  d.xnode = nullptr;  // vertex geometry only
+  d.H = H;
+  d.A = A;
+  d.adv = nullptr;    // no advection
+  d.wind = wind_xy;
+  d.ocean = ocean_xy;
+  d.v = reinterpret_cast<double *>(base + L.v);
+  d.nc = reinterpret_cast<double *>(base + L.nc);
+  d.S = base + L.S;
+  d.fe = nullptr;     // the fused strategies keep element forces in LDS
+
+  hipStream_t s = c.stream;
+  const int tx = kTileShapes[shape][0] - 1, ty = kTileShapes[shape][1] - 1;
+  // the array keeps the previous call's contents: clear this call's part
+  st = hip_status(launch_fill(base + L.flag, (L.total - L.flag) / 4, 0u, s));
+  if (st == MEVP_OK)
+    st = hip_status(launch_single_tables(D, tx, ty, doms, eblk, L.n_eblk, nblk, L.n_nblk, tiles,
+                                         L.n_tiles, s));
+  // classify the cells as mevp_set_geometry does (all parallelograms -> the
+  // constant-Jacobian kernels), waiting for the one flag
+  int *flag = d.flag + 1;
+  if (st == MEVP_OK) st = hip_status(launch_fill(flag, 1, 1u, s));
+  if (st == MEVP_OK) st = hip_status(launch_cell_shape(d, 0, D.ne, flag, s));
+  int aff = 0;
+  if (st == MEVP_OK)
+    st = hip_status(hipMemcpyAsync(&aff, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (st == MEVP_OK) st = hip_status(hipStreamSynchronize(s));
+  if (st != MEVP_OK) return st;
+  D.kind = aff ? kGeoAffine : kGeoBilinear;
+  c.tile_split.n[D.kind] = L.n_tiles;
+  c.eblk_split.n[D.kind] = L.n_eblk;
+  st = hip_status(launch_single_tables(D, tx, ty, doms, eblk, L.n_eblk, nblk, L.n_nblk, tiles,
+                                       L.n_tiles, s));
+  // state in, the step, state out
+  const size_t nS = (size_t)3 * c.ns * D.ne;
+  if (st == MEVP_OK) st = copy(v_buf(&c, 0), v_xy, sizeof(double) * 2 * D.nn, s);
+  if (st == MEVP_OK) {
+    if (precision == MEVP_FP64)
+      st = copy(S_buf(&c, 0), S, sizeof(double) * nS, s);
+    else
+      st = hip_status(launch_convert_d2f(S, static_cast<float *>(S_buf(&c, 0)), nS, s));
+  }
+  if (st == MEVP_OK) st = begin_step_on(&c, s);
+  if (st == MEVP_OK) st = subcycles_on(&c, n_subcycles, s);
+  if (st == MEVP_OK) st = copy(v_xy, v_buf(&c, c.cur), sizeof(double) * 2 * D.nn, s);
+  if (st == MEVP_OK) {
+    if (precision == MEVP_FP64)
+      st = copy(S, S_buf(&c, c.cur), sizeof(double) * nS, s);
+    else
+      st = hip_status(launch_convert_f2d(static_cast<const float *>(S_buf(&c, c.cur)), S, nS, s));
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+mevp_status mevp_step_static(const mevp_params *params, mevp_precision precision,
+                             const mevp_domain_desc *domain, const double *vertex_xy,
+                             const double *H, const double *A, const double *wind_xy,
+                             const double *ocean_xy, double *v_xy, double *S, int n_subcycles,
+                             void *hip_stream) {
+  return host_guard([&] {
+    return step_static_impl(params, precision, domain, vertex_xy, H, A, wind_xy, ocean_xy, v_xy,
+                            S, n_subcycles, hip_stream);
+  });
 }
 
 void mevp_destroy(mevp_ctx *ctx) {

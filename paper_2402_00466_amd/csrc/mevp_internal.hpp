@@ -120,6 +120,13 @@ hipError_t launch_advect_stage(const DevArrays &d, int n_a, int n_eblk, const do
                                const double *Ain, double *Hout, double *Aout, double dt, double ca,
                                double cb, hipStream_t s);
 hipError_t launch_fill(void *dst, size_t n_words32, uint32_t value, hipStream_t s);
+// Tables of a one-domain context written on the device (no host staging):
+// doms[0] = D, element and node blocks of that domain in order, and its
+// fused-kernel tiles of tx x ty owned elements in the XCD band order of the
+// host-built tables.
+hipError_t launch_single_tables(const DomDev &D, int tx, int ty, DomDev *doms, Blk *eblk,
+                                int n_eblk, Blk *nblk, int n_nblk, Tile *tiles, int n_tiles,
+                                hipStream_t s);
 // Fused subcycle launch of the parallelogram-cell tiles of one tile shape
 // (defined in mevp_affine.hpp and instantiated, for every n_s, n_a, precision
 // and tile shape the dispatch reaches, in mevp_kernels_affine*.hip: units of

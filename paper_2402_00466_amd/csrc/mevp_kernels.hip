@@ -68,6 +68,27 @@ __global__ void __launch_bounds__(kElemBlock) k_corner_vertices(DevArrays d, int
   }
 }
 
+// Tables of a one-domain context (see launch_single_tables). Tile i of the
+// launch runs on XCD i % 8 and takes tile `start + s` of the row-major tile
+// list, s = i / 8, start = the tiles dealt to the lower XCDs: every XCD gets
+// one contiguous band, as in the host-built tables.
+__global__ void k_single_tables(DomDev D, int tx, int ty, DomDev *doms, Blk *eblk, int n_eblk,
+                                Blk *nblk, int n_nblk, Tile *tiles, int n_tiles) {
+  const int stride = gridDim.x * blockDim.x;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) doms[0] = D;
+  for (int i = i0; i < n_eblk; i += stride) eblk[i] = Blk{0, i * kElemBlock};
+  for (int i = i0; i < n_nblk; i += stride) nblk[i] = Blk{0, i * kNodeBlock};
+  const int ntx = (D.nx + tx - 1) / tx;
+  for (int i = i0; i < n_tiles; i += stride) {
+    const int x = i % kNumXcd, s = i / kNumXcd;
+    int start = 0;
+    for (int xx = 0; xx < x; ++xx) start += (n_tiles - xx + kNumXcd - 1) / kNumXcd;
+    const int src = start + s;
+    tiles[i] = Tile{0, (src % ntx) * tx, (src / ntx) * ty, 0};
+  }
+}
+
 inline unsigned grid_for(size_t n, unsigned block) {
   size_t g = (n + block - 1) / block;
   if (g > 65536) g = 65536;
@@ -139,6 +160,15 @@ hipError_t launch_fill(void *dst, size_t n_words32, uint32_t value, hipStream_t 
   if (n_words32 == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3(grid_for(n_words32, 256)), dim3(256), 0, s,
                      static_cast<uint32_t *>(dst), n_words32, value);
+  return hipGetLastError();
+}
+hipError_t launch_single_tables(const DomDev &D, int tx, int ty, DomDev *doms, Blk *eblk,
+                                int n_eblk, Blk *nblk, int n_nblk, Tile *tiles, int n_tiles,
+                                hipStream_t s) {
+  int most = n_eblk > n_nblk ? n_eblk : n_nblk;
+  if (n_tiles > most) most = n_tiles;
+  hipLaunchKernelGGL(k_single_tables, dim3(grid_for((size_t)most, 256)), dim3(256), 0, s, D, tx, ty,
+                     doms, eblk, n_eblk, nblk, n_nblk, tiles, n_tiles);
   return hipGetLastError();
 }
 hipError_t launch_convert_d2f(const double *src, float *dst, size_t n, hipStream_t s) {

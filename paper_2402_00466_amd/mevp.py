@@ -60,7 +60,11 @@ EXPORTS = ["mevp_default_params", "mevp_workspace_size", "mevp_create", "mevp_se
            "mevp_set_state",
            "mevp_step", "mevp_begin_step", "mevp_subcycles", "mevp_get_state", "mevp_sync",
            "mevp_check_inputs", "mevp_check_state", "mevp_timing_enable", "mevp_timing_read",
+           "mevp_step_static",
            "mevp_destroy", "mevp_status_string", "mevp_version"]
+
+# bytes of the device array mevp_step_static works in (MEVP_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def lib_path() -> str:
@@ -105,6 +109,8 @@ def lib():
     L.mevp_check_state.argtypes = [vp]
     L.mevp_timing_enable.argtypes = [vp, i]
     L.mevp_timing_read.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.mevp_step_static.argtypes = [C.POINTER(CParams), i, C.POINTER(CDomain), dp, dp, dp, dp, dp,
+                                   dp, dp, i, vp]
     L.mevp_destroy.argtypes = [vp]
     L.mevp_status_string.argtypes = [i]
     L.mevp_version.argtypes = []
@@ -191,6 +197,33 @@ def workspace_size(domains, precision="fp64") -> int:
            lib().mevp_workspace_size(_domains_c(domains), len(domains), _PREC[precision],
                                      C.byref(out)))
     return out.value
+
+
+def step_static(domain, vertices, H, A, wind, ocean, v, S, n_subcycles: int,
+                params: Params | None = None, precision: str = "fp64", stream=None):
+    """One time step of one domain through mevp_step_static (no context, no
+    workspace, nothing allocated by the library). Every array is a contiguous
+    float64 tensor on the current device in the layouts of mevp.h; v and S
+    hold the state and are overwritten with the state after the step
+    (stream-ordered on ``stream``, default: the current torch stream)."""
+    import torch
+    d = domain if isinstance(domain, Domain) else Domain(*domain)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    shapes = {"vertices": (vertices, (2, d.nv)), "H": (H, (d.n_a, d.ne)), "A": (A, (d.n_a, d.ne)),
+              "wind": (wind, (2, d.nn)), "ocean": (ocean, (2, d.nn)), "v": (v, (2, d.nn)),
+              "S": (S, (3, d.n_s, d.ne))}
+    ptrs = []
+    for name, (t, shape) in shapes.items():
+        if not isinstance(t, torch.Tensor) or t.device != dev or t.dtype != torch.float64:
+            raise ValueError(f"{name} must be a float64 tensor on {dev}")
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous tensor of shape {shape}")
+        ptrs.append(C.c_void_p(t.data_ptr()))
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    dc = CDomain(int(d.nx), int(d.ny), int(d.n_s), int(d.n_a))
+    _check("mevp_step_static", lib().mevp_step_static(
+        C.byref((params or Params()).to_c()), _PREC[precision], C.byref(dc), *ptrs,
+        int(n_subcycles), C.c_void_p(stream.cuda_stream)))
 
 
 class Context:

@@ -162,3 +162,50 @@ def test_binding_tiles_match_the_kernel_tile_shapes():
     n = int(re.search(r"kNumTileShapes = (\d+);", src).group(1))
     assert len(shapes) == n
     assert [tuple(t) for t in mevp.TILES] == shapes
+
+
+def _step_static(M, doms=(8, 8, 6, 1), ptr=0x10000000, n=1, params=None, prec=0):
+    L = M.lib()
+    d = M.mevp.CDomain(*doms)
+    p = (params or M.Params()).to_c()
+    ptrs = [C.c_void_p(ptr)] * 7
+    return L.mevp_step_static(C.byref(p), prec, C.byref(d), *ptrs, n, None)
+
+
+def test_step_static_rejects_bad_arguments_before_device(M):
+    L = M.lib()
+    p = M.Params().to_c()
+    d = M.mevp.CDomain(8, 8, 6, 1)
+    ok = [C.c_void_p(0x10000000)] * 7
+    for k in range(7):  # each NULL array
+        ptrs = list(ok)
+        ptrs[k] = None
+        assert L.mevp_step_static(C.byref(p), 0, C.byref(d), *ptrs, 1, None) == -1
+    assert L.mevp_step_static(None, 0, C.byref(d), *ok, 1, None) == -1
+    assert L.mevp_step_static(C.byref(p), 0, None, *ok, 1, None) == -1
+    assert L.mevp_step_static(C.byref(p), 3, C.byref(d), *ok, 1, None) == -1   # precision
+    assert _step_static(M, n=-1) == -1
+    assert _step_static(M, doms=(8, 8, 5, 1)) == -1
+    bad = M.Params()
+    bad.alpha = 0.0
+    assert _step_static(M, params=bad) == -1
+
+
+def test_step_static_rejects_domains_beyond_its_array(M):
+    """The fixed device array holds ~1.1e5 elements at n_s = 6 in FP64: a
+    larger domain is ENOMEM, decided on the host before any device call."""
+    assert M.STATIC_SCRATCH_BYTES == 64 << 20
+    hdr = open(os.path.join(ROOT, "include", "mevp.h")).read()
+    assert "#define MEVP_STATIC_SCRATCH_BYTES ((size_t)64 << 20)" in hdr
+    assert _step_static(M, doms=(512, 512, 6, 1)) == -2
+    assert _step_static(M, doms=(400, 400, 6, 1)) == -2
+    assert _step_static(M, doms=(512, 512, 3, 1), prec=1) == -2
+    # the workspace of the context path is a bound from above on what it needs
+    assert M.workspace_size([M.Domain(256, 256, 6, 1)]) < 2 * M.STATIC_SCRATCH_BYTES
+
+
+def test_step_static_without_device_reports_device_error(M):
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present; the fake pointers must not reach it")
+    assert _step_static(M, doms=(64, 64, 6, 1)) == -3
