@@ -87,7 +87,7 @@ def alg_bytes(domains, precision):
     Returns (subcycle bytes, element-phase share, node-phase share); the two
     shares split the subcycle for the two-phase launch strategy (the element
     phase also reads v: 16 B per node)."""
-    ws = 4 if precision == "mixed" else 8
+    ws = 8 if precision == "fp64" else 4
     tot = be = bn = 0
     for d in domains:
         ne, nn, nv = d.nx * d.ny, (2 * d.nx + 1) * (2 * d.ny + 1), (d.nx + 1) * (d.ny + 1)
@@ -395,7 +395,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-sub", type=int, default=100)
     ap.add_argument("--workload", default="2048x2048-dg2")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "mixed_bf16"])
     ap.add_argument("--strategy", default=None,
                     choices=["fused", "two_phase", "persistent", "fused_pair", "fused_triple"],
                     help="launch strategy; default: autotuned (mevp_tune) before the timed region")
@@ -463,6 +463,8 @@ def main():
                 ("batch64-dg2", "fp64", 2, None, None), ("batch64-dg2", "mixed", 2, None, None),
                 ("2048x2048-dg2-bilinear", "fp64", 2, None, None),
                 ("2048x2048-dg2-bilinear", "mixed", 2, None, None),
+                ("2048x2048-dg2", "mixed_bf16", 3, None, None),
+                ("2048x2048-dg2-bilinear", "mixed_bf16", 2, None, None),
                 ("1024x1024-ns8", "fp64", 2, None, None), ("1024x1024-ns8", "mixed", 2, None, None),
                 ("1024x1024-dg2-iso", "fp64", 2, None, None),
                 ("1024x1024-dg2-iso", "mixed", 2, None, None),
@@ -501,6 +503,16 @@ def main():
             a, b = variants.get(f"{wl}/mixed/tuned"), variants.get(f"{wl}/fp64/tuned")
             if a and b:
                 variants[f"{wl}/mixed_speedup_over_fp64"] = a["value"] / b["value"]
+        # the bfloat16 element-matrix trial against the mixed form and FP64
+        for wl in (args.workload, "2048x2048-dg2-bilinear"):
+            bf = variants.get(f"{wl}/mixed_bf16/tuned")
+            mx = variants.get(f"{wl}/mixed/tuned")
+            f64 = variants.get(f"{wl}/fp64/tuned") or (head if wl == args.workload and
+                                                        args.precision == "fp64" else None)
+            if bf and mx:
+                variants[f"{wl}/mixed_bf16_speedup_over_mixed"] = bf["value"] / mx["value"]
+            if bf and f64:
+                variants[f"{wl}/mixed_bf16_speedup_over_fp64"] = bf["value"] / f64["value"]
 
     cpu = cpu1 = None
     if not args.no_cpu_baseline:
@@ -522,7 +534,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "mixed_bf16": "bf16 matrices+f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "precision": args.precision,
                    "strategy": head["config"]["strategy"], "tile": head["config"]["tile"],

@@ -60,9 +60,20 @@ typedef enum {
   MEVP_EHOSTMEM = -8      /* host memory allocation failed (context, tables, tuner copies) */
 } mevp_status;
 
+/* MEVP_MIXED_BF16: the bfloat16 trial of the mixed form. As MEVP_MIXED, with
+ * every entry of the element matrices -- the operators that the strain,
+ * projection and divergence contractions apply (reference basis and
+ * gradient tables, Jacobian factors, quadrature weights times |J|, the
+ * local mass matrix's factors; the listings' PSI and iMJwPSI) -- rounded to
+ * bfloat16 (8 significant bits, round to nearest even) and the arithmetic
+ * in float. n_s = 6 and n_a = 1 only (EINVAL otherwise), vertex geometry
+ * (parallelogram and bilinear cells), strategies FUSED, FUSED_PAIR and
+ * FUSED_TRIPLE. Its error against FP64 is set by the 2^-9 relative rounding
+ * of the matrices, far above the mixed form's. */
 typedef enum {
   MEVP_FP64 = 0,
-  MEVP_MIXED = 1
+  MEVP_MIXED = 1,
+  MEVP_MIXED_BF16 = 2
 } mevp_precision;
 
 /* Physical and iteration parameters (mevp_default_params fills the values
@@ -226,8 +237,8 @@ mevp_status mevp_set_forcing(mevp_ctx *ctx, int dom, const double *wind_xy,
  * coefficients that the stress update of Listing 1 and the appendix listing
  * reads and relaxes in place (Eq. (si:mevp) carries sigma^(p) from one
  * subcycle to the next; the state also carries S from one step to the next).
- * Stream-ordered copy into the current state buffers. In MEVP_MIXED, S is
- * rounded to float on the device, so S must be a device pointer there
+ * Stream-ordered copy into the current state buffers. In MEVP_MIXED and
+ * MEVP_MIXED_BF16, S is rounded to float on the device, so S must be a device pointer there
  * (EINVAL otherwise). EINVAL on a bad domain or a NULL pointer. */
 mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const double *S);
 
@@ -290,8 +301,8 @@ mevp_status mevp_get_fields(mevp_ctx *ctx, int dom, double *H, double *A);
  * velocity v and the DG stress S after the last subcycle (Eq. (si:mevp);
  * the in-out stress arguments of the appendix listing). Either pointer may be
  * NULL. Stream-ordered: the values are valid once the stream has passed the
- * call (mevp_sync). In MEVP_MIXED, S is widened from float on the device and
- * must be a device pointer (EINVAL otherwise). EINVAL on a bad domain. */
+ * call (mevp_sync). In MEVP_MIXED and MEVP_MIXED_BF16, S is widened from
+ * float on the device and must be a device pointer (EINVAL otherwise). EINVAL on a bad domain. */
 mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S);
 
 /* Wait for the context's stream; EDEVICE if any enqueued work failed. */
@@ -322,7 +333,7 @@ mevp_status mevp_timing_read(mevp_ctx *ctx, int *count, double *total_ms);
  * subcycles) of ONE domain with vertex geometry, without a context or a
  * workspace: the values are those of mevp_create + mevp_set_geometry /
  * _fields / _forcing / _state + mevp_step(n_subcycles) + mevp_get_state on
- * the same inputs (bit for bit, in both precisions).
+ * the same inputs (bit for bit, in every precision).
  * Arguments: params and precision as in mevp_create; `domain` one descriptor;
  * vertex_xy, H, A, wind_xy, ocean_xy the inputs in the layouts above, read in
  * place by the kernels; v_xy [2][(2nx+1)(2ny+1)] and S [3][n_s][nx*ny] the

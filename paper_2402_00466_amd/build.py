@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libmevp.so")
 SOURCES = ["mevp_api.hip", "mevp_kernels.hip", "mevp_kernels_ns3.hip", "mevp_kernels_ns6.hip",
-           "mevp_kernels_ns8.hip", "mevp_kernels_affine.hip", "mevp_kernels_affine_ns6_fp64.hip"]
+           "mevp_kernels_ns8.hip", "mevp_kernels_affine.hip", "mevp_kernels_affine_ns6_fp64.hip",
+           "mevp_kernels_bf16.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

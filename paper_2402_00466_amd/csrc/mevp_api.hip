@@ -113,9 +113,10 @@ struct Layout {
 
 mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout *L) {
   if (!dd || nd < 1) return MEVP_EINVAL;
-  if (prec != MEVP_FP64 && prec != MEVP_MIXED) return MEVP_EINVAL;
+  if (prec != MEVP_FP64 && prec != MEVP_MIXED && prec != MEVP_MIXED_BF16) return MEVP_EINVAL;
   const int ns = dd[0].n_s, na = dd[0].n_a;
   if (!(ns == 3 || ns == 6 || ns == 8) || !(na == 1 || na == 3 || na == 6)) return MEVP_EINVAL;
+  if (prec == MEVP_MIXED_BF16 && (ns != 6 || na != 1)) return MEVP_EINVAL;  // the trial's kernels
   long long te = 0, tn = 0, tv = 0, neb = 0, nnb = 0, ntl = 0;
   for (int i = 0; i < nd; ++i) {
     const mevp_domain_desc &d = dd[i];
@@ -139,7 +140,7 @@ mevp_status plan(const mevp_domain_desc *dd, int nd, mevp_precision prec, Layout
     if (te > kIndexMax || tn > kIndexMax || 2 * tn > kIndexMax || 18 * te > (1LL << 40))
       return MEVP_EINVAL;
   }
-  const size_t ws = (prec == MEVP_MIXED) ? sizeof(float) : sizeof(double);
+  const size_t ws = (prec == MEVP_FP64) ? sizeof(double) : sizeof(float);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -269,7 +270,7 @@ mevp_status host_guard(F &&f) noexcept {
 
 size_t s_words(const mevp_ctx *c) { return (size_t)3 * c->ns * c->tot_e; }
 size_t s_bytes(const mevp_ctx *c) {
-  return (c->prec == MEVP_MIXED ? sizeof(float) : sizeof(double));
+  return (c->prec == MEVP_FP64 ? sizeof(double) : sizeof(float));
 }
 // current / other state buffers
 double *v_buf(mevp_ctx *c, int which) { return c->d.v + (size_t)which * 2 * c->tot_n; }
@@ -491,6 +492,7 @@ mevp_status mevp_set_geometry(mevp_ctx *ctx, int dom, const double *vertex_xy) {
 
 mevp_status mevp_set_geometry_cg2(mevp_ctx *ctx, int dom, const double *node_xy) {
   if (bad_dom(ctx, dom) || !node_xy) return MEVP_EINVAL;
+  if (ctx->prec == MEVP_MIXED_BF16) return MEVP_EINVAL;  // vertex geometry only
   const DomDev &D = ctx->dom_h[dom];
   hipStream_t s = ctx->stream;
   mevp_status st = copy(const_cast<double *>(ctx->d.xnode) + 2 * (size_t)D.node_off, node_xy,
@@ -533,7 +535,7 @@ mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const dou
   if (bad_dom(ctx, dom) || !v_xy || !S) return MEVP_EINVAL;
   const DomDev &D = ctx->dom_h[dom];
   const size_t n = (size_t)3 * ctx->ns * D.ne, o = (size_t)3 * ctx->ns * D.elem_off;
-  if (ctx->prec == MEVP_MIXED) {
+  if (ctx->prec != MEVP_FP64) {
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, S) != hipSuccess || attr.type != hipMemoryTypeDevice) {
       (void)hipGetLastError();
@@ -551,7 +553,7 @@ mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const dou
 mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S) {
   if (bad_dom(ctx, dom)) return MEVP_EINVAL;
   const DomDev &D = ctx->dom_h[dom];
-  if (S && ctx->prec == MEVP_MIXED) {
+  if (S && ctx->prec != MEVP_FP64) {
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, S) != hipSuccess || attr.type != hipMemoryTypeDevice) {
       (void)hipGetLastError();
@@ -626,7 +628,7 @@ mevp_status mevp_get_launch_depth(mevp_ctx *ctx, int *depth) {
 }
 
 static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
-  const bool mixed = ctx->prec == MEVP_MIXED;
+  const int prec = ctx->prec;
   if (n == 0) return MEVP_OK;
   if (persistent_whole(ctx)) {
     const int nxt = ctx->cur ^ 1;
@@ -638,7 +640,7 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
     f.n_sub = n;
     f.depth = 1;
     const int slot = timer_start(ctx, 0);
-    hipError_t e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->tile_split,
+    hipError_t e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, prec, ctx->tile_split,
                                          f, stream);
     timer_stop(ctx, 0, slot);
     if (e == hipSuccess) {
@@ -664,7 +666,7 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
       f.n_sub = depth;
       f.depth = depth;
       const int slot = timer_start(ctx, 0);
-      e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->tile_split, f,
+      e = launch_fused_subcycle(ctx->d, ctx->kp, ctx->ns, ctx->na, prec, ctx->tile_split, f,
                                 stream);
       timer_stop(ctx, 0, slot);
       if (e == hipSuccess) ctx->cur = nxt;
@@ -673,12 +675,12 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
       const Bufs b{v_buf(ctx, ctx->cur), v_buf(ctx, ctx->cur), S_buf(ctx, ctx->cur),
                    S_buf(ctx, ctx->cur)};
       int slot = timer_start(ctx, 0);
-      e = launch_element_phase(ctx->d, ctx->kp, ctx->ns, ctx->na, mixed, ctx->eblk_split, b,
+      e = launch_element_phase(ctx->d, ctx->kp, ctx->ns, ctx->na, prec, ctx->eblk_split, b,
                                stream);
       timer_stop(ctx, 0, slot);
       if (e == hipSuccess) {
         slot = timer_start(ctx, 1);
-        e = launch_node_phase(ctx->d, ctx->kp, mixed, ctx->n_nblk, b, stream);
+        e = launch_node_phase(ctx->d, ctx->kp, prec != MEVP_FP64, ctx->n_nblk, b, stream);
         timer_stop(ctx, 1, slot);
       }
     }
@@ -748,6 +750,10 @@ mevp_status mevp_set_config(mevp_ctx *ctx, const mevp_config *cfg) {
     if (kTileShapes[sh][0] - 1 == cfg->tile_nx && kTileShapes[sh][1] - 1 == cfg->tile_ny) shape = sh;
   if (shape < 0 || (shape != 0 && ctx->na != 1)) return MEVP_EINVAL;  // see kTileShapes
   if (cfg->strategy == MEVP_STRATEGY_FUSED_TRIPLE && ctx->na != 1) return MEVP_EINVAL;
+  // the bfloat16 trial has the fused kernels only
+  if (ctx->prec == MEVP_MIXED_BF16 && (cfg->strategy == MEVP_STRATEGY_TWO_PHASE ||
+                                       cfg->strategy == MEVP_STRATEGY_PERSISTENT))
+    return MEVP_EINVAL;
   ctx->strategy = static_cast<mevp_strategy>(cfg->strategy);
   graphs_clear(ctx);
   if (shape != ctx->shape) {
@@ -944,7 +950,7 @@ static std::string tune_key(const mevp_ctx *c) {
   for (const auto &D : c->dom_h) ek[D.kind] += D.ne;
   char buf[200];
   snprintf(buf, sizeof buf, "gfx950/%s/ns%d/na%d/dom%d/el%lld/max%lldx%lld/geo%lld.%lld.%lld",
-           c->prec == MEVP_MIXED ? "mixed" : "fp64", c->ns, c->na, c->nd, ne, mx, my, ek[0], ek[1],
+           c->prec == MEVP_MIXED ? "mixed" : c->prec == MEVP_MIXED_BF16 ? "mixed_bf16" : "fp64", c->ns, c->na, c->nd, ne, mx, my, ek[0], ek[1],
            ek[2]);
   return buf;
 }
@@ -1004,7 +1010,8 @@ static mevp_status tune_impl(mevp_ctx *ctx, int n_trial, const char *cache_path,
       cand.push_back(
           mevp_config{MEVP_STRATEGY_FUSED_TRIPLE, kTileShapes[sh][0] - 1, kTileShapes[sh][1] - 1});
   }
-  cand.push_back(mevp_config{MEVP_STRATEGY_TWO_PHASE, kTileShapes[0][0] - 1, kTileShapes[0][1] - 1});
+  if (ctx->prec != MEVP_MIXED_BF16)
+    cand.push_back(mevp_config{MEVP_STRATEGY_TWO_PHASE, kTileShapes[0][0] - 1, kTileShapes[0][1] - 1});
   // PERSISTENT is not a candidate: its grid-wide barrier between subcycles
   // costs several microseconds on MI355X, while consecutive launches of a
   // replayed graph are a fraction of a microsecond apart, so it never wins
@@ -1134,7 +1141,7 @@ mevp_status plan_static(const mevp_domain_desc *dd, mevp_precision prec, int sha
   Layout full;
   mevp_status st = plan(dd, 1, prec, &full);  // validates the descriptor and precision
   if (st != MEVP_OK) return st;
-  const size_t ws = (prec == MEVP_MIXED) ? sizeof(float) : sizeof(double);
+  const size_t ws = (prec == MEVP_FP64) ? sizeof(double) : sizeof(float);
   const int tx = kTileShapes[shape][0] - 1, ty = kTileShapes[shape][1] - 1;
   L->n_eblk = full.n_eblk;
   L->n_nblk = full.n_nblk;

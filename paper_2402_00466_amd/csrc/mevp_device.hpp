@@ -40,6 +40,24 @@
 namespace mevp {
 namespace {
 
+// An entry of the element matrices -- the operators that the strain,
+// projection and divergence contractions apply to the velocities and stress
+// coefficients: reference tables, Jacobian factors, quadrature weights times
+// |J|, the local mass matrix's factors -- in the arithmetic type T. MP = 1 is
+// the bfloat16 trial of the mixed form: each entry rounded to bfloat16 (8
+// significant bits, round to nearest even), the arithmetic still in float.
+template <class T, int MP>
+__device__ __forceinline__ T mat(T x) {
+  if constexpr (MP == 0) {
+    return x;
+  } else {
+    static_assert(std::is_same<T, float>::value, "bfloat16 element matrices need float arithmetic");
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+  }
+}
+
 // Bilinear cell map from the vertices (0,0), (1,0), (0,1), (1,1) of the
 // reference square: J(xi, eta) = [[J00, J01], [J10, J11]] with
 //   J00 = (1-eta) ax + eta bx, J01 = (1-xi) cx + xi dx, and the same in y.
@@ -400,7 +418,7 @@ struct DomBufs {
 // with the zero factors (P_1 at the centre point) skipped at compile time
 // (every index is a constant after unrolling).
 // ---------------------------------------------------------------------------
-template <int NS, int NGP, class T>
+template <int NS, int NGP, class T, int MP = 0>
 struct DgGauss {
   T w[3][NGP];
   bool hw[3][NGP];
@@ -415,7 +433,7 @@ struct DgGauss {
         for (int k = 0; k < NS; ++k) {
           const double f = dg_1d(kDgX[k], Gauss1D<NGP>::x[i]);
           if (kDgY[k] != ky || f == 0.0) continue;
-          acc = have ? acc + c[k] * T(f) : c[k] * T(f);
+          acc = have ? acc + c[k] * mat<T, MP>(T(f)) : c[k] * mat<T, MP>(T(f));
           have = true;
         }
         w[ky][i] = acc;
@@ -429,7 +447,7 @@ struct DgGauss {
     for (int ky = 0; ky < 3; ++ky) {
       const double f = dg_1d(ky, Gauss1D<NGP>::x[j]);
       if (!hw[ky][i] || f == 0.0) continue;
-      acc = have ? acc + w[ky][i] * T(f) : w[ky][i] * T(f);
+      acc = have ? acc + w[ky][i] * mat<T, MP>(T(f)) : w[ky][i] * mat<T, MP>(T(f));
       have = true;
     }
     return acc;
@@ -488,7 +506,7 @@ __device__ __forceinline__ Geo<T, GK> load_geo(const DevArrays &d, const DomDev 
 // (the stress before the update). On return R holds the new stress
 // coefficients and fx, fy the forces.
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class SOld>
+template <int NS, int NA, class T, int MP = 0, class SOld>
 __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kGeoAffine> &g,
                                                const double (&Hc)[NA], const double (&Ac)[NA],
                                                const T (&vx)[9], const T (&vy)[9], SOld sold,
@@ -505,8 +523,10 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
   // E12 = ((J00 Gxe - J01 Gxx) + (J11 Gyx - J10 Gye))/(2|J|), G = the
   // reference operators applied to v and divided by the DG norm ----
   const T s4 = T(0.25) * idet, s8 = T(0.125) * idet;
-  const T a00 = J00 * s4, a01 = J01 * s4, a10 = J10 * s4, a11 = J11 * s4;
-  const T b00 = J00 * s8, b01 = J01 * s8, b10 = J10 * s8, b11 = J11 * s8;
+  const T a00 = mat<T, MP>(J00 * s4), a01 = mat<T, MP>(J01 * s4);
+  const T a10 = mat<T, MP>(J10 * s4), a11 = mat<T, MP>(J11 * s4);
+  const T b00 = mat<T, MP>(J00 * s8), b01 = mat<T, MP>(J01 * s8);
+  const T b10 = mat<T, MP>(J10 * s8), b11 = mat<T, MP>(J11 * s8);
   T EA[NS], EB[NS], EQ[NS];
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
@@ -514,12 +534,12 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       if (a_xi(k, a) != 0.0) {
-        const T c = T(a_xi(k, a) / dg_mass(k));
+        const T c = mat<T, MP>(T(a_xi(k, a) / dg_mass(k)));
         gxx += c * vx[a];
         gyx += c * vy[a];
       }
       if (a_eta(k, a) != 0.0) {
-        const T c = T(a_eta(k, a) / dg_mass(k));
+        const T c = mat<T, MP>(T(a_eta(k, a) / dg_mass(k)));
         gxe += c * vx[a];
         gye += c * vy[a];
       }
@@ -532,7 +552,7 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
 
   // ---- stress update ----
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
-  const DgGauss<NS, Ngp<NS>::value, T> gA(EA), gB(EB), gQ(EQ);
+  const DgGauss<NS, Ngp<NS>::value, T, MP> gA(EA), gB(EB), gQ(EQ);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
@@ -544,7 +564,7 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (Q::psi(k, q) != 0.0) {
-        const T pw = T(Q::w(q) * Q::psi(k, q) / dg_mass(k));
+        const T pw = mat<T, MP>(T(Q::w(q) * Q::psi(k, q) / dg_mass(k)));
         R11[k] += pw * s11;
         R12[k] += pw * s12;
         R22[k] += pw * s22;
@@ -556,12 +576,14 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
   // ---- divergence, element part: the adjugate-weighted stress per
   // coefficient first, then the transposed reference operators ----
   T Gxx[NS], Gxe[NS], Gyx[NS], Gye[NS];
+  const T m00 = mat<T, MP>(J00), m01 = mat<T, MP>(J01), m10 = mat<T, MP>(J10),
+          m11 = mat<T, MP>(J11);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    Gxx[k] = J11 * R11[k] - J01 * R12[k];
-    Gxe[k] = J00 * R12[k] - J10 * R11[k];
-    Gyx[k] = J11 * R12[k] - J01 * R22[k];
-    Gye[k] = J00 * R22[k] - J10 * R12[k];
+    Gxx[k] = m11 * R11[k] - m01 * R12[k];
+    Gxe[k] = m00 * R12[k] - m10 * R11[k];
+    Gyx[k] = m11 * R12[k] - m01 * R22[k];
+    Gye[k] = m00 * R22[k] - m10 * R12[k];
   }
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
@@ -569,12 +591,12 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (a_xi(k, a) != 0.0) {
-        const T c = T(a_xi(k, a));
+        const T c = mat<T, MP>(T(a_xi(k, a)));
         bx += c * Gxx[k];
         by += c * Gyx[k];
       }
       if (a_eta(k, a) != 0.0) {
-        const T c = T(a_eta(k, a));
+        const T c = mat<T, MP>(T(a_eta(k, a)));
         bx += c * Gxe[k];
         by += c * Gye[k];
       }
@@ -589,7 +611,7 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
 // Gauss point from the map, local mass matrix M_e = Psi W_e Psi^T factorised
 // per element. Same inputs and outputs as element_affine.
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class Map, class SOld>
+template <int NS, int NA, class T, int MP, class Map, class SOld>
 __device__ __forceinline__ void element_general_core(const KParams &p, const Map &cell,
                                                      const double (&Hc)[NA],
                                                      const double (&Ac)[NA], const T (&vx)[9],
@@ -597,21 +619,21 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
                                                      T (&R12)[NS], T (&R22)[NS], T (&fx)[9],
                                                      T (&fy)[9]);
 
-template <int NS, int NA, class T, class Map, class SOld>
+template <int NS, int NA, class T, int MP = 0, class Map, class SOld>
 __device__ __forceinline__ void element_general(const KParams &p, const Map &cell,
                                                 const double (&Hc)[NA], const double (&Ac)[NA],
                                                 const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                 T (&fx)[9], T (&fy)[9]) {
   if constexpr (std::is_same<Map, Cell<T>>::value)
-    element_general_core<NS, NA, T>(p, BilinearJ<T>(cell), Hc, Ac, vx, vy, sold, R11, R12, R22,
-                                    fx, fy);
+    element_general_core<NS, NA, T, MP>(p, BilinearJ<T>(cell), Hc, Ac, vx, vy, sold, R11, R12,
+                                        R22, fx, fy);
   else
-    element_general_core<NS, NA, T>(p, cell, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+    element_general_core<NS, NA, T, MP>(p, cell, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
 // Map: BilinearJ or Q2Map (jac, wdet, and the mass-matrix build).
-template <int NS, int NA, class T, class Map, class SOld>
+template <int NS, int NA, class T, int MP, class Map, class SOld>
 __device__ __forceinline__ void element_general_core(const KParams &p, const Map &cell,
                                                      const double (&Hc)[NA],
                                                      const double (&Ac)[NA], const T (&vx)[9],
@@ -631,25 +653,29 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       if (Q::dxi(a, q) != 0.0) {
-        gxx += T(Q::dxi(a, q)) * vx[a];
-        gyx += T(Q::dxi(a, q)) * vy[a];
+        gxx += mat<T, MP>(T(Q::dxi(a, q))) * vx[a];
+        gyx += mat<T, MP>(T(Q::dxi(a, q))) * vy[a];
       }
       if (Q::deta(a, q) != 0.0) {
-        gxe += T(Q::deta(a, q)) * vx[a];
-        gye += T(Q::deta(a, q)) * vy[a];
+        gxe += mat<T, MP>(T(Q::deta(a, q))) * vx[a];
+        gye += mat<T, MP>(T(Q::deta(a, q))) * vy[a];
       }
     }
     T J00, J01, J10, J11;
     cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+    J00 = mat<T, MP>(J00);
+    J01 = mat<T, MP>(J01);
+    J10 = mat<T, MP>(J10);
+    J11 = mat<T, MP>(J11);
     // w_q |J_q| grad v = w_q adj(J)^T (d/dxi, d/deta) v: the determinant cancels
-    const T w = T(Q::w(q));
+    const T w = mat<T, MP>(T(Q::w(q)));
     const T e11 = w * (J11 * gxx - J10 * gxe);
     const T e22 = w * (J00 * gye - J01 * gyx);
     const T e12 = T(0.5) * w * ((J00 * gxe - J01 * gxx) + (J11 * gyx - J10 * gye));
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (Q::psi(k, q) != 0.0) {
-        const T ps = T(Q::psi(k, q));
+        const T ps = mat<T, MP>(T(Q::psi(k, q)));
         E11[k] += ps * e11;
         E12[k] += ps * e12;
         E22[k] += ps * e22;
@@ -660,6 +686,14 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
   // moments are the only large arrays live
   Ldl<NS, T> mass;
   mass.template build<Q>(cell);
+  if constexpr (MP != 0) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      mass.invd[i] = mat<T, MP>(mass.invd[i]);
+#pragma unroll
+      for (int k = 0; k < i; ++k) mass.L[i][k] = mat<T, MP>(mass.L[i][k]);
+    }
+  }
   mass.solve(E11);
   mass.solve(E12);
   mass.solve(E22);
@@ -674,7 +708,7 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
 
   // ---- stress update ----
   const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
-  const DgGauss<NS, Ngp<NS>::value, T> gA(E11), gB(E22), gQ(E12);
+  const DgGauss<NS, Ngp<NS>::value, T, MP> gA(E11), gB(E22), gQ(E12);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
@@ -683,11 +717,11 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
     const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
     T s11, s12, s22;
     vp_stress<T>(p, P, gA.at(i, j), gB.at(i, j), gQ.at(i, j), s11, s12, s22);
-    const T wd = cell.wdet(Q::w(q), Q::xi(q), Q::eta(q));
+    const T wd = mat<T, MP>(cell.wdet(Q::w(q), Q::xi(q), Q::eta(q)));
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
       if (Q::psi(k, q) != 0.0) {
-        const T pw = T(Q::psi(k, q)) * wd;
+        const T pw = mat<T, MP>(T(Q::psi(k, q))) * wd;
         R11[k] += pw * s11;
         R12[k] += pw * s12;
         R22[k] += pw * s22;
@@ -703,14 +737,18 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
   //      = -sum_q (dphi_a/dxi Gxi + dphi_a/deta Geta) with G = w_q sigma adj(J)^T ----
 #pragma unroll
   for (int a = 0; a < 9; ++a) fx[a] = fy[a] = T(0);
-  const DgGauss<NS, Ngp<NS>::value, T> r11(R11), r12(R12), r22(R22);
+  const DgGauss<NS, Ngp<NS>::value, T, MP> r11(R11), r12(R12), r22(R22);
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
     const int i = q % Ngp<NS>::value, j = q / Ngp<NS>::value;
     const T s11 = r11.at(i, j), s12 = r12.at(i, j), s22 = r22.at(i, j);
     T J00, J01, J10, J11;
     cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
-    const T w = T(Q::w(q));
+    J00 = mat<T, MP>(J00);
+    J01 = mat<T, MP>(J01);
+    J10 = mat<T, MP>(J10);
+    J11 = mat<T, MP>(J11);
+    const T w = mat<T, MP>(T(Q::w(q)));
     const T gxxi = w * (s11 * J11 - s12 * J01);
     const T gxet = w * (s12 * J00 - s11 * J10);
     const T gyxi = w * (s12 * J11 - s22 * J01);
@@ -718,32 +756,32 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       if (Q::dxi(a, q) != 0.0) {
-        fx[a] -= T(Q::dxi(a, q)) * gxxi;
-        fy[a] -= T(Q::dxi(a, q)) * gyxi;
+        fx[a] -= mat<T, MP>(T(Q::dxi(a, q))) * gxxi;
+        fy[a] -= mat<T, MP>(T(Q::dxi(a, q))) * gyxi;
       }
       if (Q::deta(a, q) != 0.0) {
-        fx[a] -= T(Q::deta(a, q)) * gxet;
-        fy[a] -= T(Q::deta(a, q)) * gyet;
+        fx[a] -= mat<T, MP>(T(Q::deta(a, q))) * gxet;
+        fy[a] -= mat<T, MP>(T(Q::deta(a, q))) * gyet;
       }
     }
   }
 }
 
-template <int NS, int NA, class T, int GK, class SOld>
+template <int NS, int NA, class T, int GK, int MP = 0, class SOld>
 __device__ __forceinline__ void element_compute(const KParams &p, const Geo<T, GK> &g,
                                                 const double (&Hc)[NA], const double (&Ac)[NA],
                                                 const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                 T (&fx)[9], T (&fy)[9]) {
   if constexpr (GK == kGeoAffine)
-    element_affine<NS, NA, T>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+    element_affine<NS, NA, T, MP>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
   else
-    element_general<NS, NA, T>(p, g.map, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+    element_general<NS, NA, T, MP>(p, g.map, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
 // Element update of element el = (ex, ey) with every input read from global
 // memory (v and S of the current subcycle).
-template <int NS, int NA, class T, class TS, int GK>
+template <int NS, int NA, class T, class TS, int GK, int MP = 0>
 __device__ __forceinline__ void element_update(const DevArrays &d, const DomDev &D,
                                                const KParams &p, const double *v_in,
                                                const TS *S_in, int el, int ex, int ey,
@@ -756,7 +794,7 @@ __device__ __forceinline__ void element_update(const DevArrays &d, const DomDev 
   load_ice<NA>(d, D, el, Hc, Ac);
   const size_t ne = (size_t)D.ne;
   auto sold = [&](int c, int k) { return T(S_in[(c * NS + k) * ne + el]); };
-  element_compute<NS, NA, T, GK>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+  element_compute<NS, NA, T, GK, MP>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
 // Velocity update of one interior node:
@@ -969,7 +1007,7 @@ struct NodeBatch {
 // buffers and written to the *_out buffers (double buffering: neighbouring
 // tiles read the old values while this one writes the new).
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class TS, int GK, int EX, int EY>
+template <int NS, int NA, class T, class TS, int GK, int EX, int EY, int MP = 0>
 __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p, const Tile t,
                                            const Bufs &b, T (*fl)[EX * EY]) {
   constexpr int TX = EX - 1, TY = EY - 1, NT = EX * EY;
@@ -982,8 +1020,8 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
     if (ex >= 0 && ey >= 0 && ex < D.nx && ey < D.ny) {
       const int el = ey * D.nx + ex;
       T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
-      element_update<NS, NA, T, TS, GK>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx,
-                                        fy);
+      element_update<NS, NA, T, TS, GK, MP>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22,
+                                            fx, fy);
       if (lx > 0 && ly > 0) store_stress<NS, T, TS>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
@@ -1031,7 +1069,7 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
 // equals K single subcycles bit for bit. Only v^{p-1} / S^{p-1} are read
 // and only v^{p+K-1} / S^{p+K-1} written (double buffering as in fused_tile).
 // ---------------------------------------------------------------------------
-template <int NS, int NA, class T, class TS, int GK, int EX, int EY, int K>
+template <int NS, int NA, class T, class TS, int GK, int EX, int EY, int K, int MP = 0>
 __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
     k_fused_multi(DevArrays d, KParams p, const Tile *tiles, Bufs b) {
   static_assert(K == 2 || K == 3, "two or three subcycles per pass");
@@ -1074,11 +1112,11 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
         load_ice<NA>(d, D, el, Hc, Ac);
         load_velocity<T>(D, B.v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
         auto sold = [&](int c, int k) { return T(B.S_in[(c * NS + k) * ne + el]); };
-        element_compute<NS, NA, T, GK>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+        element_compute<NS, NA, T, GK, MP>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
       } else {
         gather_velocity<T>(vl[0], vl[1], vlds(2 * ex, 2 * ey), VW, vx, vy);
         auto sold = [&](int c, int k) { return c == 0 ? S11[k] : c == 1 ? S12[k] : S22[k]; };
-        element_compute<NS, NA, T, GK>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+        element_compute<NS, NA, T, GK, MP>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
       }
       if (i == K - 1) {
         if (lx >= K && ly >= K) store_stress<NS, T, TS>(B.S_out, ne, el, R11, R12, R22);
@@ -1154,11 +1192,11 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
 }
 
 // Fused subcycle kernel: one tile per workgroup, one subcycle.
-template <int NS, int NA, class T, class TS, int GK, int EX, int EY>
+template <int NS, int NA, class T, class TS, int GK, int EX, int EY, int MP = 0>
 __global__ void __launch_bounds__(EX *EY) k_fused(DevArrays d, KParams p, const Tile *tiles,
                                                    Bufs b) {
   __shared__ T fl[18][EX * EY];
-  fused_tile<NS, NA, T, TS, GK, EX, EY>(d, p, tiles[blockIdx.x], b, fl);
+  fused_tile<NS, NA, T, TS, GK, EX, EY, MP>(d, p, tiles[blockIdx.x], b, fl);
 }
 
 // Persistent form (cooperative launch): the workgroups stay resident for n_sub
@@ -1552,14 +1590,14 @@ inline hipError_t two_phase_t(const DevArrays &d, const KParams &p, const Launch
 
 // Fused subcycle(s): tile kernel(s) per geometry kind, in GeoKind order; f.depth 2 or 3:
 // the kernel that runs that many subcycles per pass.
-template <int NS, int NA, class T, int GK, int EX, int EY>
+template <int NS, int NA, class T, int GK, int EX, int EY, int MP = 0>
 inline hipError_t fused_one(const DevArrays &d, const KParams &p, const Tile *tiles, int ntiles,
                             const FusedArgs &f, hipStream_t s) {
   if (f.depth == 2) {
     // two subcycles per pass: parallelogram and bilinear cells (the
     // isoparametric map's 18 coordinates per lane do not fit beside them)
     if constexpr (GK != kGeoIso) {
-      hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, GK, EX, EY, 2>), dim3(ntiles),
+      hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, GK, EX, EY, 2, MP>), dim3(ntiles),
                          dim3((EX + 2) * (EY + 2)), 0, s, d, p, tiles, f.b0);
       return hipGetLastError();
     }
@@ -1569,60 +1607,79 @@ inline hipError_t fused_one(const DevArrays &d, const KParams &p, const Tile *ti
     // three subcycles per pass: built for parallelogram cells and one ice dof
     // only (the general-cell update would spill at this occupancy)
     if constexpr (NA == 1 && GK == kGeoAffine) {
-      hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, GK, EX, EY, 3>), dim3(ntiles),
+      hipLaunchKernelGGL((k_fused_multi<NS, NA, T, T, GK, EX, EY, 3, MP>), dim3(ntiles),
                          dim3((EX + 4) * (EY + 4)), 0, s, d, p, tiles, f.b0);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;
   }
   if (!f.persist) {
-    hipLaunchKernelGGL((k_fused<NS, NA, T, T, GK, EX, EY>), dim3(ntiles), dim3(EX * EY), 0, s, d,
-                       p, tiles, f.b0);
+    hipLaunchKernelGGL((k_fused<NS, NA, T, T, GK, EX, EY, MP>), dim3(ntiles), dim3(EX * EY), 0, s,
+                       d, p, tiles, f.b0);
     return hipGetLastError();
   }
-  auto kern = k_fused_persist<NS, NA, T, T, GK, EX, EY>;
-  int per_cu = 0, dev = 0, n_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, EX * EY, 0);
-  if (e == hipSuccess) e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return e;
-  int grid = per_cu * n_cu;
-  if (grid > ntiles) grid = ntiles;
-  if (grid >= kNumXcd) grid -= grid % kNumXcd;
-  if (grid < 1) return hipErrorInvalidValue;
-  DevArrays dd = d;
-  KParams pp = p;
-  const Tile *tt = tiles;
-  int nt = ntiles, ns = f.n_sub;
-  Bufs b0 = f.b0, b1 = f.b1;
-  void *args[] = {&dd, &pp, &tt, &nt, &b0, &b1, &ns};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid), dim3(EX * EY),
-                                    args, 0, s);
+  if constexpr (MP != 0) {
+    return hipErrorInvalidValue;  // no persistent form of the trial
+  } else {
+    auto kern = k_fused_persist<NS, NA, T, T, GK, EX, EY>;
+    int per_cu = 0, dev = 0, n_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, EX * EY, 0);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    int grid = per_cu * n_cu;
+    if (grid > ntiles) grid = ntiles;
+    if (grid >= kNumXcd) grid -= grid % kNumXcd;
+    if (grid < 1) return hipErrorInvalidValue;
+    DevArrays dd = d;
+    KParams pp = p;
+    const Tile *tt = tiles;
+    int nt = ntiles, ns = f.n_sub;
+    Bufs b0 = f.b0, b1 = f.b1;
+    void *args[] = {&dd, &pp, &tt, &nt, &b0, &b1, &ns};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid), dim3(EX * EY),
+                                      args, 0, s);
+  }
 }
 
-template <int NS, int NA, class T, int EX, int EY>
+// MP = 1 (the bfloat16 trial): parallelogram and bilinear cells, launched from
+// the unit that instantiates fused_t with it
+template <int NS, int NA, class T, int EX, int EY, int MP = 0>
 inline hipError_t fused_shape(const DevArrays &d, const KParams &p, const Launch &L,
                               const FusedArgs &f, hipStream_t s) {
   hipError_t e = hipSuccess;
   const Tile *t = d.tiles;
-  if (L.n[kGeoAffine] > 0) e = fused_affine<NS, NA, T, EX, EY>(d, p, t, L.n[kGeoAffine], f, s);
+  if (L.n[kGeoAffine] > 0) {
+    if constexpr (MP == 0)
+      e = fused_affine<NS, NA, T, EX, EY>(d, p, t, L.n[kGeoAffine], f, s);
+    else
+      e = fused_one<NS, NA, T, kGeoAffine, EX, EY, MP>(d, p, t, L.n[kGeoAffine], f, s);
+  }
   t += L.n[kGeoAffine];
   if (e == hipSuccess && L.n[kGeoBilinear] > 0)
-    e = fused_one<NS, NA, T, kGeoBilinear, EX, EY>(d, p, t, L.n[kGeoBilinear], f, s);
+    e = fused_one<NS, NA, T, kGeoBilinear, EX, EY, MP>(d, p, t, L.n[kGeoBilinear], f, s);
   t += L.n[kGeoBilinear];
-  if (e == hipSuccess && L.n[kGeoIso] > 0)
-    e = fused_one<NS, NA, T, kGeoIso, EX, EY>(d, p, t, L.n[kGeoIso], f, s);
+  if (e == hipSuccess && L.n[kGeoIso] > 0) {
+    if constexpr (MP == 0)
+      e = fused_one<NS, NA, T, kGeoIso, EX, EY>(d, p, t, L.n[kGeoIso], f, s);
+    else
+      e = hipErrorInvalidValue;
+  }
   return e;
 }
 
-template <int NS, int NA, class T>
+template <int NS, int NA, class T, int MP = 0>
 inline hipError_t fused_t(const DevArrays &d, const KParams &p, const Launch &L,
                           const FusedArgs &f, hipStream_t s) {
-  if (f.shape == 0) return fused_shape<NS, NA, T, kTileShapes[0][0], kTileShapes[0][1]>(d, p, L, f, s);
+  if (f.shape == 0)
+    return fused_shape<NS, NA, T, kTileShapes[0][0], kTileShapes[0][1], MP>(d, p, L, f, s);
   if constexpr (NA == 1) {  // the other tile shapes are built for one ice dof only
-    if (f.shape == 1) return fused_shape<NS, NA, T, kTileShapes[1][0], kTileShapes[1][1]>(d, p, L, f, s);
-    if (f.shape == 2) return fused_shape<NS, NA, T, kTileShapes[2][0], kTileShapes[2][1]>(d, p, L, f, s);
-    if (f.shape == 3) return fused_shape<NS, NA, T, kTileShapes[3][0], kTileShapes[3][1]>(d, p, L, f, s);
+    if (f.shape == 1)
+      return fused_shape<NS, NA, T, kTileShapes[1][0], kTileShapes[1][1], MP>(d, p, L, f, s);
+    if (f.shape == 2)
+      return fused_shape<NS, NA, T, kTileShapes[2][0], kTileShapes[2][1], MP>(d, p, L, f, s);
+    if (f.shape == 3)
+      return fused_shape<NS, NA, T, kTileShapes[3][0], kTileShapes[3][1], MP>(d, p, L, f, s);
   }
   return hipErrorInvalidValue;
 }

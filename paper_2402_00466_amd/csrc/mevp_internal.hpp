@@ -107,12 +107,14 @@ constexpr int kNumXcd = 8;
 // Launchers (mevp_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int n_s,
                              const double *v, int n_nblk, hipStream_t s);
+// prec: a mevp_precision (0 FP64, 1 mixed, 2 mixed with bfloat16 element
+// matrices, fused kernels at n_s = 6 and n_a = 1 only)
 hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, int n_a,
-                                bool mixed, const Launch &L, Bufs b, hipStream_t s);
+                                int prec, const Launch &L, Bufs b, hipStream_t s);
 hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, int n_nblk, Bufs b,
                              hipStream_t s);
 hipError_t launch_fused_subcycle(const DevArrays &d, const KParams &p, int n_s, int n_a,
-                                 bool mixed, const Launch &L, const FusedArgs &f, hipStream_t s);
+                                 int prec, const Launch &L, const FusedArgs &f, hipStream_t s);
 hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s);
 hipError_t launch_corner_vertices(const DevArrays &d, int dom, int nv, hipStream_t s);
 hipError_t launch_advect_stage(const DevArrays &d, int n_a, int n_eblk, const double *v,
@@ -144,6 +146,9 @@ hipError_t two_phase_ns8(const DevArrays &, const KParams &, int, bool, const La
 hipError_t fused_ns3(const DevArrays &, const KParams &, int, bool, const Launch &, const FusedArgs &, hipStream_t);
 hipError_t fused_ns6(const DevArrays &, const KParams &, int, bool, const Launch &, const FusedArgs &, hipStream_t);
 hipError_t fused_ns8(const DevArrays &, const KParams &, int, bool, const Launch &, const FusedArgs &, hipStream_t);
+// the bfloat16 element-matrix trial (mevp_kernels_bf16.hip)
+hipError_t fused_bf16(const DevArrays &, const KParams &, int n_s, int n_a, const Launch &,
+                      const FusedArgs &, hipStream_t);
 hipError_t launch_convert_d2f(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_convert_f2d(const float *src, double *dst, size_t n, hipStream_t s);
 hipError_t launch_check_finite(const double *p, size_t n, int *flag, int bit, hipStream_t s);

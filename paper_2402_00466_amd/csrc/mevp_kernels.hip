@@ -110,16 +110,21 @@ hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, int n_a, bool mixed,
+hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, int n_a, int prec,
                                 const Launch &L, Bufs b, hipStream_t s) {
+  if (prec != 0 && prec != 1) return hipErrorInvalidValue;
+  const bool mixed = prec == 1;
   if (n_s == 3) return two_phase_ns3(d, p, n_a, mixed, L, b, s);
   if (n_s == 6) return two_phase_ns6(d, p, n_a, mixed, L, b, s);
   if (n_s == 8) return two_phase_ns8(d, p, n_a, mixed, L, b, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fused_subcycle(const DevArrays &d, const KParams &p, int n_s, int n_a, bool mixed,
+hipError_t launch_fused_subcycle(const DevArrays &d, const KParams &p, int n_s, int n_a, int prec,
                                  const Launch &L, const FusedArgs &f, hipStream_t s) {
+  if (prec == 2) return fused_bf16(d, p, n_s, n_a, L, f, s);
+  if (prec != 0 && prec != 1) return hipErrorInvalidValue;
+  const bool mixed = prec == 1;
   if (n_s == 3) return fused_ns3(d, p, n_a, mixed, L, f, s);
   if (n_s == 6) return fused_ns6(d, p, n_a, mixed, L, f, s);
   if (n_s == 8) return fused_ns8(d, p, n_a, mixed, L, f, s);

@@ -209,3 +209,15 @@ def test_step_static_without_device_reports_device_error(M):
     if torch.cuda.device_count() > 0:
         pytest.skip("a device is present; the fake pointers must not reach it")
     assert _step_static(M, doms=(64, 64, 6, 1)) == -3
+
+
+def test_bf16_precision_sizes_and_limits(M):
+    """The bfloat16 trial stores the stress in float like the mixed form and
+    exists for n_s = 6, n_a = 1 only (EINVAL before any device call)."""
+    D = M.Domain
+    assert M.workspace_size([D(64, 32, 6, 1)], "mixed_bf16") == M.workspace_size([D(64, 32, 6, 1)], "mixed")
+    for d in (D(8, 8, 3, 1), D(8, 8, 8, 1), D(8, 8, 6, 3)):
+        with pytest.raises(M.MevpError) as ei:
+            M.workspace_size([d], "mixed_bf16")
+        assert ei.value.status == -1
+    assert _step_static(M, doms=(8, 8, 3, 1), prec=2) == -1
