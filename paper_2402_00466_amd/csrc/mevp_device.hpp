@@ -242,6 +242,38 @@ __device__ __forceinline__ double ice_strength(const KParams &p, const double (&
   return p.Pstar * h * exp(-p.C * (1.0 - a));
 }
 
+// The ice fields of one element as the stress update reads them: the DG
+// coefficients of H and A, and with one coefficient each (constant fields)
+// the ice strength, the same at every Gauss point, evaluated once when the
+// element is loaded instead of in every subcycle.
+template <int NA>
+struct Ice {
+  double H[NA], A[NA];
+  double P0;
+  template <class Q>
+  __device__ __forceinline__ double P(const KParams &p, int q) const {
+    if constexpr (NA == 1)
+      return P0;
+    else
+      return ice_strength<NA, Q>(p, H, A, q);
+  }
+};
+
+template <int NA>
+__device__ __forceinline__ Ice<NA> load_ice(const DevArrays &d, const DomDev &D, const KParams &p,
+                                            int el) {
+  Ice<NA> ice;
+  const size_t ne = (size_t)D.ne;
+#pragma unroll
+  for (int k = 0; k < NA; ++k) {
+    ice.H[k] = d.H[((size_t)NA * D.elem_off) + k * ne + el];
+    ice.A[k] = d.A[((size_t)NA * D.elem_off) + k * ne + el];
+  }
+  // psi_0 = 1 at every point, so the rule does not matter for one coefficient
+  ice.P0 = NA == 1 ? ice_strength<NA, Quad<3>>(p, ice.H, ice.A, 0) : 0.0;
+  return ice;
+}
+
 // 1/sqrt(x) for a normal x > 0: the hardware estimate refined by two Newton
 // steps y <- y + y (1 - x y^2) / 2, each doubling the number of correct bits.
 __device__ __forceinline__ double rsqrt_nr(double x) {
@@ -358,17 +390,6 @@ __device__ __forceinline__ Q2Map<T> load_q2map(const DomDev &D, const double *xn
   return m;
 }
 
-template <int NA>
-__device__ __forceinline__ void load_ice(const DevArrays &d, const DomDev &D, int el,
-                                         double (&Hc)[NA], double (&Ac)[NA]) {
-  const size_t ne = (size_t)D.ne;
-#pragma unroll
-  for (int k = 0; k < NA; ++k) {
-    Hc[k] = d.H[((size_t)NA * D.elem_off) + k * ne + el];
-    Ac[k] = d.A[((size_t)NA * D.elem_off) + k * ne + el];
-  }
-}
-
 // Relaxation of Listing 1: R <- fac S_old + ainv R (R holds Pi_e(s) on entry);
 // sold(c, k) is coefficient k of stress component c (11, 12, 22) before the
 // update, in T.
@@ -463,6 +484,7 @@ struct Geo;
 template <class T>
 struct Geo<T, kGeoAffine> {
   T J00, J01, J10, J11;
+  T idet;  // 1 / |J|
 };
 template <class T>
 struct Geo<T, kGeoBilinear> {
@@ -486,6 +508,7 @@ __device__ __forceinline__ Geo<T, GK> load_geo(const DevArrays &d, const DomDev 
     g.J10 = T(VY[i0 + 1] - Y0);
     g.J01 = T(VX[i2] - X0);
     g.J11 = T(VY[i2] - Y0);
+    g.idet = T(1) / (g.J00 * g.J11 - g.J01 * g.J10);
     return g;
   } else if constexpr (GK == kGeoBilinear) {
     return Geo<T, kGeoBilinear>{load_cell<T>(D, d.vert, ex, ey)};
@@ -508,14 +531,14 @@ __device__ __forceinline__ Geo<T, GK> load_geo(const DevArrays &d, const DomDev 
 // ---------------------------------------------------------------------------
 template <int NS, int NA, class T, int MP = 0, class SOld>
 __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kGeoAffine> &g,
-                                               const double (&Hc)[NA], const double (&Ac)[NA],
+                                               const Ice<NA> &ice,
                                                const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                T (&fx)[9], T (&fy)[9]) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
   const T J00 = g.J00, J01 = g.J01, J10 = g.J10, J11 = g.J11;
-  const T idet = T(1) / (J00 * J11 - J01 * J10);
+  const T idet = g.idet;
 
   // ---- strain, projected, in the stress update's variables (vp_stress):
   // EA = (E11 + E22)/4, EB = (E11 - E22)/8, EQ = E12/4 per coefficient, with
@@ -551,14 +574,13 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
   }
 
   // ---- stress update ----
-  const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
   const DgGauss<NS, Ngp<NS>::value, T, MP> gA(EA), gB(EB), gQ(EQ);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
     const int i = q % Ngp<NS>::value, j = q / Ngp<NS>::value;
-    const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
+    const double P = ice.template P<Q>(p, q);
     T s11, s12, s22;
     vp_stress<T>(p, P, gA.at(i, j), gB.at(i, j), gQ.at(i, j), s11, s12, s22);
 #pragma unroll
@@ -613,30 +635,28 @@ __device__ __forceinline__ void element_affine(const KParams &p, const Geo<T, kG
 // ---------------------------------------------------------------------------
 template <int NS, int NA, class T, int MP, class Map, class SOld>
 __device__ __forceinline__ void element_general_core(const KParams &p, const Map &cell,
-                                                     const double (&Hc)[NA],
-                                                     const double (&Ac)[NA], const T (&vx)[9],
+                                                     const Ice<NA> &ice, const T (&vx)[9],
                                                      const T (&vy)[9], SOld sold, T (&R11)[NS],
                                                      T (&R12)[NS], T (&R22)[NS], T (&fx)[9],
                                                      T (&fy)[9]);
 
 template <int NS, int NA, class T, int MP = 0, class Map, class SOld>
 __device__ __forceinline__ void element_general(const KParams &p, const Map &cell,
-                                                const double (&Hc)[NA], const double (&Ac)[NA],
+                                                const Ice<NA> &ice,
                                                 const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                 T (&fx)[9], T (&fy)[9]) {
   if constexpr (std::is_same<Map, Cell<T>>::value)
-    element_general_core<NS, NA, T, MP>(p, BilinearJ<T>(cell), Hc, Ac, vx, vy, sold, R11, R12,
-                                        R22, fx, fy);
+    element_general_core<NS, NA, T, MP>(p, BilinearJ<T>(cell), ice, vx, vy, sold, R11, R12, R22,
+                                        fx, fy);
   else
-    element_general_core<NS, NA, T, MP>(p, cell, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+    element_general_core<NS, NA, T, MP>(p, cell, ice, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
 // Map: BilinearJ or Q2Map (jac, wdet, and the mass-matrix build).
 template <int NS, int NA, class T, int MP, class Map, class SOld>
 __device__ __forceinline__ void element_general_core(const KParams &p, const Map &cell,
-                                                     const double (&Hc)[NA],
-                                                     const double (&Ac)[NA], const T (&vx)[9],
+                                                     const Ice<NA> &ice, const T (&vx)[9],
                                                      const T (&vy)[9], SOld sold, T (&R11)[NS],
                                                      T (&R12)[NS], T (&R22)[NS], T (&fx)[9],
                                                      T (&fy)[9]) {
@@ -707,14 +727,13 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
   }
 
   // ---- stress update ----
-  const double P0 = ice_strength<NA, Q>(p, Hc, Ac, 0);
   const DgGauss<NS, Ngp<NS>::value, T, MP> gA(E11), gB(E22), gQ(E12);
 #pragma unroll
   for (int k = 0; k < NS; ++k) R11[k] = R12[k] = R22[k] = T(0);
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
     const int i = q % Ngp<NS>::value, j = q / Ngp<NS>::value;
-    const double P = (NA == 1) ? P0 : ice_strength<NA, Q>(p, Hc, Ac, q);
+    const double P = ice.template P<Q>(p, q);
     T s11, s12, s22;
     vp_stress<T>(p, P, gA.at(i, j), gB.at(i, j), gQ.at(i, j), s11, s12, s22);
     const T wd = mat<T, MP>(cell.wdet(Q::w(q), Q::xi(q), Q::eta(q)));
@@ -769,14 +788,14 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
 
 template <int NS, int NA, class T, int GK, int MP = 0, class SOld>
 __device__ __forceinline__ void element_compute(const KParams &p, const Geo<T, GK> &g,
-                                                const double (&Hc)[NA], const double (&Ac)[NA],
+                                                const Ice<NA> &ice,
                                                 const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
                                                 T (&fx)[9], T (&fy)[9]) {
   if constexpr (GK == kGeoAffine)
-    element_affine<NS, NA, T, MP>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+    element_affine<NS, NA, T, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
   else
-    element_general<NS, NA, T, MP>(p, g.map, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+    element_general<NS, NA, T, MP>(p, g.map, ice, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
 // Element update of element el = (ex, ey) with every input read from global
@@ -790,11 +809,10 @@ __device__ __forceinline__ void element_update(const DevArrays &d, const DomDev 
   const Geo<T, GK> g = load_geo<T, GK>(d, D, ex, ey);
   T vx[9], vy[9];
   load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
-  double Hc[NA], Ac[NA];
-  load_ice<NA>(d, D, el, Hc, Ac);
+  const Ice<NA> ice = load_ice<NA>(d, D, p, el);
   const size_t ne = (size_t)D.ne;
   auto sold = [&](int c, int k) { return T(S_in[(c * NS + k) * ne + el]); };
-  element_compute<NS, NA, T, GK, MP>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+  element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
 // Velocity update of one interior node:
@@ -1098,7 +1116,7 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
   const int el = exists ? ey * D.nx + ex : 0;
 
   Geo<T, GK> g{};
-  double Hc[NA], Ac[NA];
+  Ice<NA> ice{};
   T S11[NS], S12[NS], S22[NS];  // the lane's stress, as stored (rounded to TS)
   auto vlds = [&](int ix, int iy) { return (iy - jy0) * VW + (ix - jx0); };
 #pragma unroll
@@ -1109,14 +1127,14 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
       T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
       if (i == 0) {
         g = load_geo<T, GK>(d, D, ex, ey);
-        load_ice<NA>(d, D, el, Hc, Ac);
+        ice = load_ice<NA>(d, D, p, el);
         load_velocity<T>(D, B.v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
         auto sold = [&](int c, int k) { return T(B.S_in[(c * NS + k) * ne + el]); };
-        element_compute<NS, NA, T, GK, MP>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+        element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
       } else {
         gather_velocity<T>(vl[0], vl[1], vlds(2 * ex, 2 * ey), VW, vx, vy);
         auto sold = [&](int c, int k) { return c == 0 ? S11[k] : c == 1 ? S12[k] : S22[k]; };
-        element_compute<NS, NA, T, GK, MP>(p, g, Hc, Ac, vx, vy, sold, R11, R12, R22, fx, fy);
+        element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
       }
       if (i == K - 1) {
         if (lx >= K && ly >= K) store_stress<NS, T, TS>(B.S_out, ne, el, R11, R12, R22);
