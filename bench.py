@@ -62,7 +62,9 @@ KERNEL_SOURCES = ["paper_2402_00466_amd/csrc/mevp_device.hpp",
                   "paper_2402_00466_amd/csrc/mevp_affine.hpp",
                   "paper_2402_00466_amd/build.py",
                   "paper_2402_00466_amd/csrc/mevp_ref.hpp",
-                  "paper_2402_00466_amd/csrc/mevp_internal.hpp"]
+                  "paper_2402_00466_amd/csrc/mevp_internal.hpp",
+                  "paper_2402_00466_amd/csrc/mevp_index.hpp",
+                  "paper_2402_00466_amd/csrc/mevp_kernels_bf16.hip"]
 
 
 def log(*a):

@@ -34,6 +34,7 @@
 
 #include <type_traits>
 
+#include "mevp_index.hpp"
 #include "mevp_internal.hpp"
 #include "mevp_ref.hpp"
 
@@ -949,18 +950,16 @@ struct NodeBatch {
     const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
     const size_t nn = (size_t)D.nn;
     const int w = ix1 - ix0, n = w * (iy1 - iy0);
-    // k / w via a float reciprocal: for k < 2^13 and w < 2^7 the product
-    // (k + 1/2) (1/w) is within 1e-3 of (k + 1/2) / w, which lies at least
-    // 1/(2w) from an integer, so the truncation is exact
     static_assert(R * NT <= 8192, "node rounds beyond the exact float division");
     const float rw = 1.0f / (float)w;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int k = tid + m * NT;
       act[m] = k < n;
-      const int qy = act[m] ? (int)(((float)k + 0.5f) * rw) : 0;
-      ixs[m] = ix0 + (act[m] ? k - qy * w : 0);
-      iys[m] = iy0 + qy;
+      int dx, dy;
+      node_in_range(act[m] ? k : 0, w, rw, dx, dy);
+      ixs[m] = ix0 + dx;
+      iys[m] = iy0 + dy;
       jn[m] = iys[m] * NX + ixs[m];
       bnd[m] = ixs[m] == 0 || iys[m] == 0 || ixs[m] == NX - 1 || iys[m] == NY - 1;
       if (act[m] && !bnd[m]) {
@@ -993,13 +992,13 @@ struct NodeBatch {
       // stays inside fl (any row, le + FW + 1 < NF + FW) and its value is
       // replaced by +0.0, so the sum, in ascending element order, is the one
       // over the elements that exist.
-      const bool two_x = !(ix & 1), two_y = !(iy & 1);
-      const int b3 = two_y ? 6 : 3, c0 = two_x ? 2 : 1;
-      const T *f = &fl[0][0] + (((iy - 1) >> 1) - ey0) * FW + ((ix - 1) >> 1) - ex0;
-      const T x00 = f[(b3 + c0) * NF], x01 = f[b3 * NF + 1], x10 = f[c0 * NF + FW],
-              x11 = f[FW + 1];
-      const T y00 = f[(9 + b3 + c0) * NF], y01 = f[(9 + b3) * NF + 1],
-              y10 = f[(9 + c0) * NF + FW], y11 = f[9 * NF + FW + 1];
+      int off[4];
+      bool two_x, two_y;
+      node_force_offsets(ix, iy, ex0, ey0, FW, NF, off, two_x, two_y);
+      const T *f = &fl[0][0];
+      const T x00 = f[off[0]], x01 = f[off[1]], x10 = f[off[2]], x11 = f[off[3]];
+      const T y00 = f[9 * NF + off[0]], y01 = f[9 * NF + off[1]], y10 = f[9 * NF + off[2]],
+              y11 = f[9 * NF + off[3]];
       double Fx = 0.0 + (double)x00, Fy = 0.0 + (double)y00;
       Fx += two_x ? (double)x01 : 0.0;
       Fy += two_x ? (double)y01 : 0.0;
@@ -1051,9 +1050,8 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
   // ---- nodes owned by the tile: loads before the barrier, update after ----
   const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
   const size_t nn = (size_t)D.nn;
-  const int ix0 = 2 * t.x0, iy0 = 2 * t.y0;
-  const int ix1 = (t.x0 + TX >= D.nx) ? NX : ix0 + 2 * TX;
-  const int iy1 = (t.y0 + TY >= D.ny) ? NY : iy0 + 2 * TY;
+  const NodeRange own = owned_nodes(t.x0, t.y0, TX, TY, D.nx, D.ny, NX, NY);
+  const int ix0 = own.ix0, ix1 = own.ix1, iy0 = own.iy0, iy1 = own.iy1;
   constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;
   auto uin = [&](int, int, int j, double &ux, double &uy) {
     ux = B.v_in[j];
@@ -1156,9 +1154,8 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
     if constexpr (!kEarly) __syncthreads();
     if (i < K - 1) {
       // nodes of element phase i+1: [2 (x0-K+i+1), 2 (x0+TX+K-2-i)]
-      const int ix0 = max(2 * (ex0 + i + 1), 0), iy0 = max(2 * (ey0 + i + 1), 0);
-      const int ix1 = min(2 * (t.x0 + TX + K - 2 - i) + 1, NX);
-      const int iy1 = min(2 * (t.y0 + TY + K - 2 - i) + 1, NY);
+      const NodeRange nr = multi_phase_nodes(t.x0, t.y0, TX, TY, K, i, NX, NY);
+      const int ix0 = nr.ix0, ix1 = nr.ix1, iy0 = nr.iy0, iy1 = nr.iy1;
       constexpr int R = (VW * VH + NT - 1) / NT;
       auto out = [&](int ix, int iy, int, double vx, double vy) {
         const int q = vlds(ix, iy);
@@ -1187,9 +1184,8 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
       }
     } else {
       // the owned nodes, v to global memory
-      const int ix0 = 2 * t.x0, iy0 = 2 * t.y0;
-      const int ix1 = (t.x0 + TX >= D.nx) ? NX : ix0 + 2 * TX;
-      const int iy1 = (t.y0 + TY >= D.ny) ? NY : iy0 + 2 * TY;
+      const NodeRange own = owned_nodes(t.x0, t.y0, TX, TY, D.nx, D.ny, NX, NY);
+      const int ix0 = own.ix0, ix1 = own.ix1, iy0 = own.iy0, iy1 = own.iy1;
       constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;
       auto uin = [&](int ix, int iy, int, double &ux, double &uy) {
         const int q = vlds(ix, iy);
