@@ -666,6 +666,47 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
 
   // ---- strain ----
   T E11[NS], E12[NS], E22[NS];
+  if constexpr (Map::kLinearDet) {
+    // bilinear cell: J00 = J00c + t tx, J10 = J10c + t ty, J01 = J01c + s tx,
+    // J11 = J11c + s ty, so the moments sum_q w psi_k adj(J)^T grad v are the
+    // exact constant operators a_xi, a_xi_s, a_eta, a_eta_t applied to v and
+    // combined with the cell's coefficients (no Gauss-point loop)
+    const T J00c = mat<T, MP>(cell.J00c), J01c = mat<T, MP>(cell.J01c);
+    const T J10c = mat<T, MP>(cell.J10c), J11c = mat<T, MP>(cell.J11c);
+    const T tx = mat<T, MP>(cell.tx), ty = mat<T, MP>(cell.ty);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      T xi_x = 0, xis_x = 0, eta_x = 0, etat_x = 0, xi_y = 0, xis_y = 0, eta_y = 0, etat_y = 0;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        if (a_xi(k, a) != 0.0) {
+          const T c = mat<T, MP>(T(a_xi(k, a)));
+          xi_x += c * vx[a];
+          xi_y += c * vy[a];
+        }
+        if (a_xi_s(k, a) != 0.0) {
+          const T c = mat<T, MP>(T(a_xi_s(k, a)));
+          xis_x += c * vx[a];
+          xis_y += c * vy[a];
+        }
+        if (a_eta(k, a) != 0.0) {
+          const T c = mat<T, MP>(T(a_eta(k, a)));
+          eta_x += c * vx[a];
+          eta_y += c * vy[a];
+        }
+        if (a_eta_t(k, a) != 0.0) {
+          const T c = mat<T, MP>(T(a_eta_t(k, a)));
+          etat_x += c * vx[a];
+          etat_y += c * vy[a];
+        }
+      }
+      // int psi_k (J11 dvx/dxi - J10 dvx/deta) and the like
+      E11[k] = (J11c * xi_x + ty * xis_x) - (J10c * eta_x + ty * etat_x);
+      E22[k] = (J00c * eta_y + tx * etat_y) - (J01c * xi_y + tx * xis_y);
+      E12[k] = T(0.5) * (((J00c * eta_x + tx * etat_x) - (J01c * xi_x + tx * xis_x)) +
+                         ((J11c * xi_y + ty * xis_y) - (J10c * eta_y + ty * etat_y)));
+    }
+  } else {
 #pragma unroll
   for (int k = 0; k < NS; ++k) E11[k] = E12[k] = E22[k] = T(0);
 #pragma unroll
@@ -702,6 +743,7 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
         E22[k] += ps * e22;
       }
     }
+  }
   }
   // factorised only now: the velocities are dead, so the factor and the strain
   // moments are the only large arrays live
@@ -755,6 +797,55 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
 
   // ---- divergence, element part: f[a] = -sum_q w_q |J_q| sigma(q) grad phi_a(q)
   //      = -sum_q (dphi_a/dxi Gxi + dphi_a/deta Geta) with G = w_q sigma adj(J)^T ----
+  if constexpr (Map::kLinearDet) {
+    // bilinear cell: with sigma = sum_k R[k] psi_k and the affine Jacobian
+    // entries, f[a] = -sum_k (a_xi Gc + a_xi_s Gt + a_eta Hc + a_eta_t Ht)[k][a]
+    // with per-coefficient combinations G, H of the new stress
+    const T J00c = mat<T, MP>(cell.J00c), J01c = mat<T, MP>(cell.J01c);
+    const T J10c = mat<T, MP>(cell.J10c), J11c = mat<T, MP>(cell.J11c);
+    const T tx = mat<T, MP>(cell.tx), ty = mat<T, MP>(cell.ty);
+    // coefficient by coefficient (eight combinations live at a time), each
+    // node's sums accumulated over k
+    T bx[9], by[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) bx[a] = by[a] = T(0);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const T Gxc = J11c * R11[k] - J01c * R12[k], Gxt = ty * R11[k] - tx * R12[k];
+      const T Hxc = J00c * R12[k] - J10c * R11[k], Hxt = tx * R12[k] - ty * R11[k];
+      const T Gyc = J11c * R12[k] - J01c * R22[k], Gyt = ty * R12[k] - tx * R22[k];
+      const T Hyc = J00c * R22[k] - J10c * R12[k], Hyt = tx * R22[k] - ty * R12[k];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        if (a_xi(k, a) != 0.0) {
+          const T c = mat<T, MP>(T(a_xi(k, a)));
+          bx[a] += c * Gxc;
+          by[a] += c * Gyc;
+        }
+        if (a_xi_s(k, a) != 0.0) {
+          const T c = mat<T, MP>(T(a_xi_s(k, a)));
+          bx[a] += c * Gxt;
+          by[a] += c * Gyt;
+        }
+        if (a_eta(k, a) != 0.0) {
+          const T c = mat<T, MP>(T(a_eta(k, a)));
+          bx[a] += c * Hxc;
+          by[a] += c * Hyc;
+        }
+        if (a_eta_t(k, a) != 0.0) {
+          const T c = mat<T, MP>(T(a_eta_t(k, a)));
+          bx[a] += c * Hxt;
+          by[a] += c * Hyt;
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      fx[a] = -bx[a];
+      fy[a] = -by[a];
+    }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 9; ++a) fx[a] = fy[a] = T(0);
   const DgGauss<NS, Ngp<NS>::value, T, MP> r11(R11), r12(R12), r22(R22);

@@ -121,6 +121,18 @@ constexpr double dg_1d(int i, double x) {
 // reference square (local node a = 3 b + c).
 constexpr double a_xi(int k, int a) { return kI1[kDgX[k]][a % 3] * kI0[kDgY[k]][a / 3]; }
 constexpr double a_eta(int k, int a) { return kI0[kDgX[k]][a % 3] * kI1[kDgY[k]][a / 3]; }
+
+// The same with the coordinate of the derivative's direction as a weight,
+// for bilinear cells, whose Jacobian entries are affine in one coordinate:
+//   I1s[i][c] = int P_i s L_c',
+//   AxiS[k][a] = int psi_k s dphi_a/dxi,  AetaT[k][a] = int psi_k t dphi_a/deta
+// (exact: the integrands have degree <= 4 per direction, which the Gauss rules
+// of the general path also integrate exactly).
+constexpr double kI1s[3][3] = {{1.0 / 3.0, -2.0 / 3.0, 1.0 / 3.0},
+                               {-1.0 / 12.0, 0.0, 1.0 / 12.0},
+                               {1.0 / 45.0, -2.0 / 45.0, 1.0 / 45.0}};
+constexpr double a_xi_s(int k, int a) { return kI1s[kDgX[k]][a % 3] * kI0[kDgY[k]][a / 3]; }
+constexpr double a_eta_t(int k, int a) { return kI0[kDgX[k]][a % 3] * kI1s[kDgY[k]][a / 3]; }
 constexpr double dg_mass(int k) { return kNorm1D[kDgX[k]] * kNorm1D[kDgY[k]]; }
 
 }  // namespace mevp
