@@ -698,18 +698,18 @@ mevp_status mevp_subcycles(mevp_ctx *ctx, int n) {
 mevp_status mevp_advect(mevp_ctx *ctx) {
   if (!ctx) return MEVP_EINVAL;
   if (!inputs_set(ctx)) return MEVP_ESTATE;
-  // element blocks in any order cover every element of every domain
-  const int nb = (int)ctx->eblk_h.size();
+  // the element blocks (grouped by geometry kind) cover every element of every domain
   const size_t n = (size_t)ctx->na * ctx->tot_e;
   double *H = const_cast<double *>(ctx->d.H), *A = const_cast<double *>(ctx->d.A);
   double *H1 = ctx->d.adv, *A1 = H1 + n, *H2 = A1 + n, *A2 = H2 + n;
   const double *v = v_buf(ctx, ctx->cur), dt = ctx->params.dt;
   hipStream_t s = ctx->stream;
-  hipError_t e = launch_advect_stage(ctx->d, ctx->na, nb, v, H, A, H, A, H1, A1, dt, 0.0, 1.0, s);
+  const Launch &L = ctx->eblk_split;
+  hipError_t e = launch_advect_stage(ctx->d, ctx->na, L, v, H, A, H, A, H1, A1, dt, 0.0, 1.0, s);
   if (e == hipSuccess)
-    e = launch_advect_stage(ctx->d, ctx->na, nb, v, H, A, H1, A1, H2, A2, dt, 0.75, 0.25, s);
+    e = launch_advect_stage(ctx->d, ctx->na, L, v, H, A, H1, A1, H2, A2, dt, 0.75, 0.25, s);
   if (e == hipSuccess)
-    e = launch_advect_stage(ctx->d, ctx->na, nb, v, H, A, H2, A2, H, A, dt, 1.0 / 3.0, 2.0 / 3.0, s);
+    e = launch_advect_stage(ctx->d, ctx->na, L, v, H, A, H2, A2, H, A, dt, 1.0 / 3.0, 2.0 / 3.0, s);
   return hip_status(e);
 }
 

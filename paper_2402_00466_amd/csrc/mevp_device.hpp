@@ -1469,11 +1469,16 @@ __device__ __forceinline__ void dg_grad_ref(int k, double xi, double eta, double
   ge = (k == 2) ? 1.0 : (k == 5) ? 2.0 * t : (k == 4) ? s : 0.0;
 }
 
+// Point values at compile-time points (after unrolling every basis value is a
+// constant): terms whose basis value is zero are skipped, which leaves every
+// sum of finite values unchanged bit for bit (a CG2 function on an edge
+// depends on the edge's three nodes only).
 template <int NA>
 __device__ __forceinline__ double dg_eval(const double (&c)[NA], double xi, double eta) {
   double u = 0.0;
 #pragma unroll
-  for (int k = 0; k < NA; ++k) u += c[k] * dg_fn(k, xi, eta);
+  for (int k = 0; k < NA; ++k)
+    if (dg_fn(k, xi, eta) != 0.0) u += c[k] * dg_fn(k, xi, eta);
   return u;
 }
 
@@ -1484,6 +1489,7 @@ __device__ __forceinline__ void cg2_eval(const double (&vx)[9], const double (&v
 #pragma unroll
   for (int a = 0; a < 9; ++a) {
     const double ph = q2_1d(a % 3, xi) * q2_1d(a / 3, eta);
+    if (ph == 0.0) continue;
     ux += vx[a] * ph;
     uy += vy[a] * ph;
   }
@@ -1497,7 +1503,9 @@ __device__ __forceinline__ void advect_element(const DevArrays &d, const DomDev 
                                                const double *Ain, double *Hout, double *Aout,
                                                double dt, double ca, double cb);
 
-template <int NA>
+// One kernel per cell geometry (GK: vertex cells or curved cells), launched on
+// that kind's element blocks, so that each keeps its own register budget.
+template <int NA, int GK>
 __global__ void __launch_bounds__(kElemBlock) k_advect(DevArrays d, const Blk *blks,
                                                        const double *v, const double *Hn,
                                                        const double *An, const double *Hin,
@@ -1509,7 +1517,7 @@ __global__ void __launch_bounds__(kElemBlock) k_advect(DevArrays d, const Blk *b
   const int el = blk.first + (int)threadIdx.x;
   if (el >= D.ne) return;
   const int ex = el % D.nx, ey = el / D.nx;
-  if (D.kind == kGeoIso)
+  if constexpr (GK == kGeoIso)
     advect_element<NA>(d, D, load_q2map<double>(D, d.xnode, ex, ey), true, el, ex, ey, v, Hn,
                        An, Hin, Ain, Hout, Aout, dt, ca, cb);
   else
@@ -1559,9 +1567,11 @@ __device__ __forceinline__ void advect_element(const DevArrays &d, const DomDev 
       for (int k = 0; k < NA; ++k) {
         double gx, ge;
         dg_grad_ref(k, xi, eta, gx, ge);
-        const double vg = w * (ux * (J11 * gx - J10 * ge) + uy * (J00 * ge - J01 * gx));
-        R[0][k] += uh * vg;
-        R[1][k] += ua * vg;
+        if (gx != 0.0 || ge != 0.0) {  // psi_0 is constant: no volume term
+          const double vg = w * (ux * (J11 * gx - J10 * ge) + uy * (J00 * ge - J01 * gx));
+          R[0][k] += uh * vg;
+          R[1][k] += ua * vg;
+        }
 #pragma unroll
         for (int l = 0; l < NA; ++l) M[k][l] += w * det * dg_fn(k, xi, eta) * dg_fn(l, xi, eta);
       }

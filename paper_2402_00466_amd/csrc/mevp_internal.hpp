@@ -117,7 +117,8 @@ hipError_t launch_fused_subcycle(const DevArrays &d, const KParams &p, int n_s, 
                                  int prec, const Launch &L, const FusedArgs &f, hipStream_t s);
 hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s);
 hipError_t launch_corner_vertices(const DevArrays &d, int dom, int nv, hipStream_t s);
-hipError_t launch_advect_stage(const DevArrays &d, int n_a, int n_eblk, const double *v,
+// one advection stage over the element blocks, grouped by geometry kind as in L
+hipError_t launch_advect_stage(const DevArrays &d, int n_a, const Launch &L, const double *v,
                                const double *Hn, const double *An, const double *Hin,
                                const double *Ain, double *Hout, double *Aout, double dt, double ca,
                                double cb, hipStream_t s);

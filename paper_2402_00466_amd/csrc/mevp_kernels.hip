@@ -140,19 +140,27 @@ hipError_t launch_node_phase(const DevArrays &d, const KParams &p, bool mixed, i
   return hipGetLastError();
 }
 
-hipError_t launch_advect_stage(const DevArrays &d, int n_a, int n_eblk, const double *v,
+hipError_t launch_advect_stage(const DevArrays &d, int n_a, const Launch &L, const double *v,
                                const double *Hn, const double *An, const double *Hin,
                                const double *Ain, double *Hout, double *Aout, double dt, double ca,
                                double cb, hipStream_t s) {
+  if (n_a != 1 && n_a != 3 && n_a != 6) return hipErrorInvalidValue;
+  // element blocks grouped by geometry kind: vertex cells (parallelogram and
+  // bilinear), then curved cells
+  const int n_vert = L.n[kGeoAffine] + L.n[kGeoBilinear], n_iso = L.n[kGeoIso];
+  const Blk *bv = d.eblk, *bi = d.eblk + n_vert;
 #define MEVP_AD(NA_)                                                                          \
   if (n_a == NA_) {                                                                           \
-    hipLaunchKernelGGL((k_advect<NA_>), dim3(n_eblk), dim3(kElemBlock), 0, s, d, d.eblk, v, Hn, \
-                       An, Hin, Ain, Hout, Aout, dt, ca, cb);                                  \
-    return hipGetLastError();                                                                 \
+    if (n_vert > 0)                                                                           \
+      hipLaunchKernelGGL((k_advect<NA_, kGeoBilinear>), dim3(n_vert), dim3(kElemBlock), 0, s, d, \
+                         bv, v, Hn, An, Hin, Ain, Hout, Aout, dt, ca, cb);                   \
+    if (n_iso > 0)                                                                            \
+      hipLaunchKernelGGL((k_advect<NA_, kGeoIso>), dim3(n_iso), dim3(kElemBlock), 0, s, d, bi, \
+                         v, Hn, An, Hin, Ain, Hout, Aout, dt, ca, cb);                       \
   }
   MEVP_AD(1) MEVP_AD(3) MEVP_AD(6)
 #undef MEVP_AD
-  return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_cell_shape(const DevArrays &d, int dom, int ne, int *flag, hipStream_t s) {
