@@ -227,6 +227,22 @@ struct Ldl {
   }
 };
 
+// The local mass matrix of a general cell factorised (entries rounded to
+// bfloat16 for MP = 1, as the element update uses them).
+template <int NS, class T, int MP, class Map>
+__device__ __forceinline__ void factor_mass(const Map &cell, Ldl<NS, T> &mass) {
+  using Q = Quad<Ngp<NS>::value>;
+  mass.template build<Q>(cell);
+  if constexpr (MP != 0) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      mass.invd[i] = mat<T, MP>(mass.invd[i]);
+#pragma unroll
+      for (int k = 0; k < i; ++k) mass.L[i][k] = mat<T, MP>(mass.L[i][k]);
+    }
+  }
+}
+
 // Ice strength at Gauss point q: P = P* max(0, H Psi) exp(-C (1 - min(1, max(0, A Psi))))
 // (clamps and formula of the stress listings), always in double.
 template <int NA, class Q>
@@ -639,19 +655,20 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
                                                      const Ice<NA> &ice, const T (&vx)[9],
                                                      const T (&vy)[9], SOld sold, T (&R11)[NS],
                                                      T (&R12)[NS], T (&R22)[NS], T (&fx)[9],
-                                                     T (&fy)[9]);
+                                                     T (&fy)[9], const Ldl<NS, T> *pre);
 
 template <int NS, int NA, class T, int MP = 0, class Map, class SOld>
 __device__ __forceinline__ void element_general(const KParams &p, const Map &cell,
                                                 const Ice<NA> &ice,
                                                 const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
-                                                T (&fx)[9], T (&fy)[9]) {
+                                                T (&fx)[9], T (&fy)[9],
+                                                const Ldl<NS, T> *pre = nullptr) {
   if constexpr (std::is_same<Map, Cell<T>>::value)
     element_general_core<NS, NA, T, MP>(p, BilinearJ<T>(cell), ice, vx, vy, sold, R11, R12, R22,
-                                        fx, fy);
+                                        fx, fy, pre);
   else
-    element_general_core<NS, NA, T, MP>(p, cell, ice, vx, vy, sold, R11, R12, R22, fx, fy);
+    element_general_core<NS, NA, T, MP>(p, cell, ice, vx, vy, sold, R11, R12, R22, fx, fy, pre);
 }
 
 // Map: BilinearJ or Q2Map (jac, wdet, and the mass-matrix build).
@@ -660,7 +677,7 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
                                                      const Ice<NA> &ice, const T (&vx)[9],
                                                      const T (&vy)[9], SOld sold, T (&R11)[NS],
                                                      T (&R12)[NS], T (&R22)[NS], T (&fx)[9],
-                                                     T (&fy)[9]) {
+                                                     T (&fy)[9], const Ldl<NS, T> *pre) {
   using Q = Quad<Ngp<NS>::value>;
   constexpr int NG = Q::NG;
 
@@ -747,16 +764,9 @@ __device__ __forceinline__ void element_general_core(const KParams &p, const Map
   }
   // factorised only now: the velocities are dead, so the factor and the strain
   // moments are the only large arrays live
-  Ldl<NS, T> mass;
-  mass.template build<Q>(cell);
-  if constexpr (MP != 0) {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      mass.invd[i] = mat<T, MP>(mass.invd[i]);
-#pragma unroll
-      for (int k = 0; k < i; ++k) mass.L[i][k] = mat<T, MP>(mass.L[i][k]);
-    }
-  }
+  Ldl<NS, T> built;
+  if (!pre) factor_mass<NS, T, MP>(cell, built);
+  const Ldl<NS, T> &mass = pre ? *pre : built;
   mass.solve(E11);
   mass.solve(E12);
   mass.solve(E22);
@@ -883,11 +893,12 @@ __device__ __forceinline__ void element_compute(const KParams &p, const Geo<T, G
                                                 const Ice<NA> &ice,
                                                 const T (&vx)[9], const T (&vy)[9], SOld sold,
                                                 T (&R11)[NS], T (&R12)[NS], T (&R22)[NS],
-                                                T (&fx)[9], T (&fy)[9]) {
+                                                T (&fx)[9], T (&fy)[9],
+                                                const Ldl<NS, T> *pre = nullptr) {
   if constexpr (GK == kGeoAffine)
     element_affine<NS, NA, T, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
   else
-    element_general<NS, NA, T, MP>(p, g.map, ice, vx, vy, sold, R11, R12, R22, fx, fy);
+    element_general<NS, NA, T, MP>(p, g.map, ice, vx, vy, sold, R11, R12, R22, fx, fy, pre);
 }
 
 // Element update of element el = (ex, ey) with every input read from global
@@ -1206,6 +1217,7 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
 
   Geo<T, GK> g{};
   Ice<NA> ice{};
+  Ldl<NS, T> lmass;  // bilinear cells: the local mass factor, once per pass
   T S11[NS], S12[NS], S22[NS];  // the lane's stress, as stored (rounded to TS)
   auto vlds = [&](int ix, int iy) { return (iy - jy0) * VW + (ix - jx0); };
 #pragma unroll
@@ -1219,11 +1231,21 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
         ice = load_ice<NA>(d, D, p, el);
         load_velocity<T>(D, B.v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
         auto sold = [&](int c, int k) { return T(B.S_in[(c * NS + k) * ne + el]); };
-        element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
+        if constexpr (GK == kGeoBilinear) {
+          factor_mass<NS, T, MP>(BilinearJ<T>(g.map), lmass);
+          element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy,
+                                             &lmass);
+        } else {
+          element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
+        }
       } else {
         gather_velocity<T>(vl[0], vl[1], vlds(2 * ex, 2 * ey), VW, vx, vy);
         auto sold = [&](int c, int k) { return c == 0 ? S11[k] : c == 1 ? S12[k] : S22[k]; };
-        element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
+        if constexpr (GK == kGeoBilinear)
+          element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy,
+                                             &lmass);
+        else
+          element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
       }
       if (i == K - 1) {
         if (lx >= K && ly >= K) store_stress<NS, T, TS>(B.S_out, ne, el, R11, R12, R22);
