@@ -17,6 +17,7 @@ benchmark times) unless named:
   256x256-dg2    1 step (four launch configurations) and 10 steps, FP64 and mixed
   1024x1024-dg2  1 step x 100 subcycles, FP64 and mixed
   2048x2048-dg2  1 step x 100 subcycles, FP64 and mixed
+  batch64-dg2    1 step x 100 subcycles, FP64 and mixed (three domains checked)
 """
 import copy
 
@@ -126,3 +127,36 @@ def test_stated_length_within_oracle_noise_floor(name, steps, precision, seeds):
     whole 100-subcycle step at 1024 x 1024 and 2048 x 2048), in the tuned
     launch configuration, FP64 and mixed precision against the FP64 oracle."""
     _check(name, steps, precision, "tuned", None, seeds)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch64_whole_step_within_oracle_noise_floor(precision):
+    """The 64-domain batch (sides 64 to 512 on 512 km squares: 8 km to 1 km
+    cells) for one whole 100-subcycle step in one context, in the tuned launch
+    configuration; the smallest, a middle and the largest domain against the
+    oracle beside its noise floor (2 perturbation seeds each)."""
+    import oracle
+    doms = named_workload("batch64-dg2")
+    log(f"batch64-dg2, 1 step x {N_SUB} subcycles, {precision} tuned, {len(doms)} domains")
+    res = gpu_run(doms, 1, N_SUB, precision=precision, strategy="tuned")
+    eps = 1e-15 if precision == "fp64" else 1e-7
+    for k in (0, 31, 63):
+        d = doms[k]
+        m = oracle_mesh(d)
+        run = lambda H: m.run(oracle.Params(), H, d.A, d.wind, d.ocean, 1, N_SUB)
+        ref = run(d.H)
+        floor = dict.fromkeys(FIELDS, 0.0)
+        for seed in range(2):
+            rng = np.random.default_rng(seed)
+            e = field_errors(*run(d.H * (1.0 + eps * rng.standard_normal(d.H.shape))), *ref)
+            floor = {f: max(floor[f], e[f]) for f in FIELDS}
+        err = field_errors(*res[k], *ref)
+        log(f"  domain {k} ({d.nx}x{d.ny}) gpu vs oracle: " +
+            " ".join(f"{f}={err[f]:.2e}" for f in FIELDS))
+        log(f"  domain {k} oracle floor (eps {eps:g}): " +
+            " ".join(f"{f}={floor[f]:.2e}" for f in FIELDS))
+        assert np.abs(ref[0]).max() > 1e-3
+        bad = {f: (err[f], floor[f]) for f in FIELDS
+               if not err[f] <= max(MARGIN * floor[f], 1e-12 if precision == "fp64" else 1e-5)}
+        assert not bad, f"domain {k}: above {MARGIN:g} x the oracle's noise floor: {bad}"
