@@ -136,7 +136,7 @@ typedef enum {
 } mevp_strategy;
 
 /* Launch configuration: strategy and the fused kernels' tile of owned
- * elements per workgroup (16 x 14; with n_a = 1 also 16 x 16, 32 x 14 and
+ * elements per workgroup (16 x 14; with n_a = 1 also 16 x 16, 32 x 15 and
  * 13 x 13). */
 typedef struct {
   int strategy;  /* a mevp_strategy */

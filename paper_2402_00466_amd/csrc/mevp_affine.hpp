@@ -15,7 +15,7 @@ hipError_t fused_affine(const DevArrays &d, const KParams &p, const Tile *tiles,
 
 static_assert(kNumTileShapes == 4 && kTileShapes[0][0] == 17 && kTileShapes[0][1] == 15 &&
                   kTileShapes[1][0] == 17 && kTileShapes[1][1] == 17 && kTileShapes[2][0] == 33 &&
-                  kTileShapes[2][1] == 15 && kTileShapes[3][0] == 14 && kTileShapes[3][1] == 14,
+                  kTileShapes[2][1] == 16 && kTileShapes[3][0] == 14 && kTileShapes[3][1] == 14,
               "the instantiations follow kTileShapes");
 
 }  // namespace mevp
@@ -29,4 +29,4 @@ static_assert(kNumTileShapes == 4 && kTileShapes[0][0] == 17 && kTileShapes[0][1
 // every n_a and tile shape of one n_s and precision
 #define MEVP_FA_ALL(NS_, T_)                                                              \
   MEVP_FA(NS_, 1, T_, 17, 15) MEVP_FA(NS_, 3, T_, 17, 15) MEVP_FA(NS_, 6, T_, 17, 15)     \
-  MEVP_FA(NS_, 1, T_, 17, 17) MEVP_FA(NS_, 1, T_, 33, 15) MEVP_FA(NS_, 1, T_, 14, 14)
+  MEVP_FA(NS_, 1, T_, 17, 17) MEVP_FA(NS_, 1, T_, 33, 16) MEVP_FA(NS_, 1, T_, 14, 14)

@@ -96,11 +96,13 @@ constexpr int kNodeBlock = 256;
 // fused kernel tile shapes (elements per workgroup including the one-element
 // halo; the owned block is one smaller in each direction): 17 x 15 (16 x 14
 // owned, 16 owned elements = one 128-byte line of a double array per row),
-// 17 x 17, 33 x 15 and 14 x 14 (13 x 13 owned: two subcycles per launch take
-// 16 x 16 lanes, exactly four waves, so that two workgroups share a CU at the
-// general-cell update's two waves per SIMD)
+// 17 x 17, 33 x 16 (32 x 15 owned: three subcycles per launch take 37 x 20
+// lanes, twelve waves, all that three waves per SIMD allow, and 149 KB of LDS)
+// and 14 x 14 (13 x 13 owned: two subcycles per launch take 16 x 16 lanes,
+// exactly four waves, so that two workgroups share a CU at the general-cell
+// update's two waves per SIMD)
 constexpr int kNumTileShapes = 4;
-constexpr int kTileShapes[kNumTileShapes][2] = {{17, 15}, {17, 17}, {33, 15}, {14, 14}};
+constexpr int kTileShapes[kNumTileShapes][2] = {{17, 15}, {17, 17}, {33, 16}, {14, 14}};
 // workgroups are dealt to the 8 XCDs of the chip in turn
 constexpr int kNumXcd = 8;
 

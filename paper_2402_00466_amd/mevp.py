@@ -21,7 +21,7 @@ MIXED_BF16 = 2  # mixed precision with bfloat16 element matrices (a trial; see m
 STRATEGIES = {"fused": 0, "two_phase": 1, "persistent": 2, "fused_pair": 3,
               "fused_triple": 4}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
-TILES = [(16, 14), (16, 16), (32, 14), (13, 13)]
+TILES = [(16, 14), (16, 16), (32, 15), (13, 13)]
 _PREC = {"fp64": FP64, "f64": FP64, "mixed": MIXED, "mixed_bf16": MIXED_BF16}
 
 STATUS = {0: "MEVP_OK", -1: "MEVP_EINVAL", -2: "MEVP_ENOMEM", -3: "MEVP_EDEVICE",

@@ -197,7 +197,7 @@ static void check_shape(const Domain &D, int K) {
 int main() {
   static_assert(kNumTileShapes == 4, "the shapes below follow kTileShapes");
   const int sizes[][2] = {{1, 1},   {1, 37},  {37, 1},  {2, 2},   {3, 5},    {13, 13},
-                          {14, 14}, {16, 14}, {17, 9},  {32, 14}, {33, 15},  {47, 31},
+                          {14, 14}, {16, 14}, {17, 9},  {32, 15}, {33, 16},  {47, 31},
                           {65, 29}, {100, 3}, {128, 96}, {173, 61}};
   int cases = 0;
   for (const auto &sz : sizes) {

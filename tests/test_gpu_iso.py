@@ -74,7 +74,7 @@ def test_iso_launch_configs_agree_bitwise(precision):
     d = make_domain(173, 61, 6, 1, seed=62, h=2e3, curved=0.15)
     state = random_state(d.nx, d.ny, d.n_s, seed=5)
     ref = gpu_run([d], 2, 25, precision=precision, states=[state])[0]
-    for strategy, tile in [("two_phase", None), ("fused", (16, 16)), ("fused", (32, 14)),
+    for strategy, tile in [("two_phase", None), ("fused", (16, 16)), ("fused", (32, 15)),
                            ("persistent", (16, 14)), ("fused_pair", (16, 14)),
                            ("fused_triple", (16, 16)), ("fused_pair", (13, 13))]:
         got = gpu_run([d], 2, 25, precision=precision, states=[state], strategy=strategy,
