@@ -1429,10 +1429,23 @@ __global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams 
       sh[m] = h_int;
       sa[m] = a_int;
     };
-    if (D.kind == kGeoIso)
+    if (D.kind == kGeoIso) {
       integrals(load_q2map<double>(D, d.xnode, exc, eyc));
-    else
+    } else if (NA == 1 && D.kind == kGeoAffine) {
+      // parallelogram cell, constant fields: |J|, h and a are constants, and
+      // the rule integrates the product of the two quadratics L_c, L_b
+      // exactly, to the Simpson weights 1/6, 2/3, 1/6 of [0, 1]
+      const Cell<double> cell = load_cell<double>(D, d.vert, exc, eyc);
+      double J00, J01, J10, J11;
+      cell.jac(0.5, 0.5, J00, J01, J10, J11);
+      const double det = J00 * J11 - J01 * J10;
+      const double wa = (cc == 1 ? 2.0 / 3.0 : 1.0 / 6.0) * (bb == 1 ? 2.0 / 3.0 : 1.0 / 6.0);
+      const double h = fmax(0.0, Hc[0]), ac = fmin(1.0, fmax(0.0, Ac[0]));
+      sh[m] = wa * det * p.rho_i * h;
+      sa[m] = wa * det * ac;
+    } else {
       integrals(load_cell<double>(D, d.vert, exc, eyc));
+    }
   }
   double MH = 0.0, mA = 0.0;
 #pragma unroll
