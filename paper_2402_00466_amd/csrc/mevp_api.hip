@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "mevp.h"
+#include "mevp_index.hpp"
 #include "mevp_internal.hpp"
 
 using namespace mevp;
@@ -229,15 +230,20 @@ void order_blocks(mevp_ctx *c) {
       if (c->dom_h[i].kind != kind) continue;
       const DomDev &D = c->dom_h[i];
       for (int f = 0; f < D.ne; f += kElemBlock) c->eblk_h.push_back(Blk{i, f});
-      for (int y0 = 0; y0 < D.ny; y0 += TY)
-        for (int x0 = 0; x0 < D.nx; x0 += TX) c->tiles_h.push_back(Tile{i, x0, y0, 0});
+      const int ntx = (D.nx + TX - 1) / TX, nty = (D.ny + TY - 1) / TY;
+      for (int k = 0; k < ntx * nty; ++k) {
+        int col, row;
+        strip_tile(k, ntx, nty, kStripTiles, col, row);
+        c->tiles_h.push_back(Tile{i, col * TX, row * TY, 0});
+      }
     }
     c->eblk_split.n[kind] = (int)(c->eblk_h.size() - e0);
     c->tile_split.n[kind] = (int)(c->tiles_h.size() - t0);
   }
   // Workgroup i of a launch runs on XCD i % 8. Permute each launch's tiles so
-  // that every XCD gets one contiguous band of tiles: neighbouring tiles share
-  // halo elements and cache lines, which then meet in the same L2.
+  // that every XCD gets one contiguous band of the strip-ordered list:
+  // neighbouring tiles share halo elements and cache lines, which then meet in
+  // the same L2.
   auto xcd_order = [](Tile *t, int n) {
     std::vector<Tile> src(t, t + n);
     int start = 0;

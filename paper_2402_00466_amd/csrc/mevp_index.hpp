@@ -1,9 +1,9 @@
 // mevp_index.hpp -- index arithmetic of the fused tile kernels, shared by the
-// kernels (mevp_device.hpp) and the host-side index check (tests/index_check.hip):
-// the node ranges of each node phase, the node-to-lane mapping of a node
-// phase, and the LDS offsets of the element forces a node sums. Host and
-// device run the same functions, so the check covers the kernels' own
-// arithmetic.
+// kernels (mevp_device.hpp), the host runtime (mevp_api.hip) and the host-side
+// index check (tests/index_check.hip): the node ranges of each node phase, the
+// node-to-lane mapping of a node phase, the LDS offsets of the element forces
+// a node sums, and the order of a domain's tiles. Host and device run the
+// same functions, so the check covers the kernels' own arithmetic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,6 +42,17 @@ __host__ __device__ inline NodeRange multi_phase_nodes(int x0, int y0, int TX, i
   r.ix1 = c < NX ? c : NX;
   r.iy1 = e < NY ? e : NY;
   return r;
+}
+
+// Tile k of a domain's tile list of ntx x nty tiles in strip order: column
+// strips `strip` tiles wide (the last one narrower), row by row within a
+// strip, left to right within a row; (col, row) of that tile.
+__host__ __device__ inline void strip_tile(int k, int ntx, int nty, int strip, int &col, int &row) {
+  const int j = k / (strip * nty);
+  const int w = ntx - strip * j < strip ? ntx - strip * j : strip;
+  const int off = k - strip * j * nty;
+  row = off / w;
+  col = strip * j + off % w;
 }
 
 // Node k of a range w nodes wide, row-major: (k mod w, k div w), the

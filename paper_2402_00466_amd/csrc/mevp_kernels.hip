@@ -69,9 +69,9 @@ __global__ void __launch_bounds__(kElemBlock) k_corner_vertices(DevArrays d, int
 }
 
 // Tables of a one-domain context (see launch_single_tables). Tile i of the
-// launch runs on XCD i % 8 and takes tile `start + s` of the row-major tile
-// list, s = i / 8, start = the tiles dealt to the lower XCDs: every XCD gets
-// one contiguous band, as in the host-built tables.
+// launch runs on XCD i % 8 and takes tile `start + s` of the strip-ordered
+// tile list, s = i / 8, start = the tiles dealt to the lower XCDs: every XCD
+// gets one contiguous band, as in the host-built tables.
 __global__ void k_single_tables(DomDev D, int tx, int ty, DomDev *doms, Blk *eblk, int n_eblk,
                                 Blk *nblk, int n_nblk, Tile *tiles, int n_tiles) {
   const int stride = gridDim.x * blockDim.x;
@@ -79,13 +79,14 @@ __global__ void k_single_tables(DomDev D, int tx, int ty, DomDev *doms, Blk *ebl
   if (i0 == 0) doms[0] = D;
   for (int i = i0; i < n_eblk; i += stride) eblk[i] = Blk{0, i * kElemBlock};
   for (int i = i0; i < n_nblk; i += stride) nblk[i] = Blk{0, i * kNodeBlock};
-  const int ntx = (D.nx + tx - 1) / tx;
+  const int ntx = (D.nx + tx - 1) / tx, nty = (D.ny + ty - 1) / ty;
   for (int i = i0; i < n_tiles; i += stride) {
     const int x = i % kNumXcd, s = i / kNumXcd;
     int start = 0;
     for (int xx = 0; xx < x; ++xx) start += (n_tiles - xx + kNumXcd - 1) / kNumXcd;
-    const int src = start + s;
-    tiles[i] = Tile{0, (src % ntx) * tx, (src / ntx) * ty, 0};
+    int col, row;
+    strip_tile(start + s, ntx, nty, kStripTiles, col, row);
+    tiles[i] = Tile{0, col * tx, row * ty, 0};
   }
 }
 

@@ -14,7 +14,8 @@
 //     the node phase before it; no node is written twice in one phase;
 //   * the float-reciprocal node division equals integer division;
 //   * over all tiles, every CG2 node is stored exactly once and every
-//     element's stress exactly once, at in-range global indices.
+//     element's stress exactly once, at in-range global indices;
+//   * the strip order of a domain's tiles lists every tile exactly once.
 // Prints "ok <cases>" and exits 0, or the first failure and exits 1.
 #include <stdio.h>
 #include <stdlib.h>
@@ -179,6 +180,28 @@ static void check_multi(const Domain &D, std::vector<int> &node_seen, std::vecto
     }
 }
 
+// The strip order of a domain's tiles lists every tile of the ntx x nty grid
+// exactly once, column strips of kStripTiles left to right, rows bottom to
+// top within a strip.
+static void check_strip_order(int ntx, int nty) {
+  std::vector<int> seen((size_t)ntx * nty, 0);
+  int prev_strip = 0, prev_row = 0, prev_col = -1;
+  for (int k = 0; k < ntx * nty; ++k) {
+    int col, row;
+    strip_tile(k, ntx, nty, kStripTiles, col, row);
+    CHECK(col >= 0 && col < ntx && row >= 0 && row < nty, "tile %d of %dx%d -> (%d, %d)", k, ntx,
+          nty, col, row);
+    CHECK(seen[(size_t)row * ntx + col]++ == 0, "tile (%d, %d) listed twice", col, row);
+    const int strip = col / kStripTiles;
+    CHECK(strip > prev_strip || (strip == prev_strip && (row > prev_row ||
+                                                         (row == prev_row && col > prev_col))),
+          "tile %d of %dx%d out of strip order", k, ntx, nty);
+    prev_strip = strip;
+    prev_row = row;
+    prev_col = col;
+  }
+}
+
 template <int EX, int EY>
 static void check_shape(const Domain &D, int K) {
   std::vector<int> node_seen(D.nn, 0), el_seen(D.ne, 0);
@@ -208,6 +231,13 @@ int main() {
     D.NY = 2 * D.ny + 1;
     D.ne = D.nx * D.ny;
     D.nn = D.NX * D.NY;
+    for (int sh = 0; sh < kNumTileShapes; ++sh) {
+      const int tx = kTileShapes[sh][0] - 1, ty = kTileShapes[sh][1] - 1;
+      check_strip_order((D.nx + tx - 1) / tx, (D.ny + ty - 1) / ty);
+    }
+    check_strip_order(65, 3);
+    check_strip_order(16, 5);
+    check_strip_order(47, 31);
     for (int K = 1; K <= 3; ++K) {
       check_shape<kTileShapes[0][0], kTileShapes[0][1]>(D, K);
       check_shape<kTileShapes[1][0], kTileShapes[1][1]>(D, K);
