@@ -50,9 +50,11 @@ MALL_BYTES = 256 << 20         # MI355X Infinity Cache (last-level, all XCDs)
 FP64_FLOP_PER_ELEMENT_SUBCYCLE = 1600.0
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")  # measured bytes per launch
 METRIC = "element-subcycles/sec (FP64 vs mixed/batched) + achieved HBM GB/s vs peak"
-# every source file that holds device code, and the build script with its
-# compiler flags (the traffic records are tied to a hash of them)
-KERNEL_SOURCES = ["paper_2402_00466_amd/csrc/mevp_device.hpp",
+# every source file that holds device code, the build script with its
+# compiler flags and the runtime that orders the tiles (the traffic records
+# are tied to a hash of them)
+KERNEL_SOURCES = ["paper_2402_00466_amd/csrc/mevp_api.hip",
+                  "paper_2402_00466_amd/csrc/mevp_device.hpp",
                   "paper_2402_00466_amd/csrc/mevp_kernels.hip",
                   "paper_2402_00466_amd/csrc/mevp_kernels_ns3.hip",
                   "paper_2402_00466_amd/csrc/mevp_kernels_ns6.hip",
