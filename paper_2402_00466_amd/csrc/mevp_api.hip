@@ -233,7 +233,7 @@ void order_blocks(mevp_ctx *c) {
       const int ntx = (D.nx + TX - 1) / TX, nty = (D.ny + TY - 1) / TY;
       for (int k = 0; k < ntx * nty; ++k) {
         int col, row;
-        strip_tile(k, ntx, nty, kStripTiles, col, row);
+        strip_tile(k, ntx, nty, strip_width(TX, kStripElems), col, row);
         c->tiles_h.push_back(Tile{i, col * TX, row * TY, 0});
       }
     }

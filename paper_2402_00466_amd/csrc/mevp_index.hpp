@@ -44,6 +44,13 @@ __host__ __device__ inline NodeRange multi_phase_nodes(int x0, int y0, int TX, i
   return r;
 }
 
+// Tiles per strip for tiles of tx owned elements in x: about kStripElems
+// elements (at least one tile).
+__host__ __device__ inline int strip_width(int tx, int strip_elems) {
+  const int w = (strip_elems + tx / 2) / tx;
+  return w > 0 ? w : 1;
+}
+
 // Tile k of a domain's tile list of ntx x nty tiles in strip order: column
 // strips `strip` tiles wide (the last one narrower), row by row within a
 // strip, left to right within a row; (col, row) of that tile.

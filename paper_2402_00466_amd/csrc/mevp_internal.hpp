@@ -105,12 +105,13 @@ constexpr int kNumTileShapes = 4;
 constexpr int kTileShapes[kNumTileShapes][2] = {{17, 15}, {17, 17}, {33, 16}, {14, 14}};
 // workgroups are dealt to the 8 XCDs of the chip in turn
 constexpr int kNumXcd = 8;
-// A domain's tiles are listed in column strips of kStripTiles tiles, row by
-// row within a strip, before the list is cut into one contiguous band per XCD:
-// the 32 CUs of an XCD then run two consecutive rows of one strip at a time,
-// so the tiles beside and below a tile (which read the same halo elements and
-// nodes) run with it or just before it, while those lines are in the XCD's L2
-constexpr int kStripTiles = 16;
+// A domain's tiles are listed in column strips about kStripElems elements
+// wide (strip_width tiles), row by row within a strip, before the list is cut
+// into one contiguous band per XCD: the workgroups an XCD runs at once then
+// cover a few consecutive rows of one strip, so the tiles beside and below a
+// tile (which read the same halo elements and nodes) run with it or just
+// before it, while those lines are in the XCD's L2
+constexpr int kStripElems = 256;
 
 // Launchers (mevp_kernels.hip). Return hipSuccess or the launch error.
 hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int n_s,

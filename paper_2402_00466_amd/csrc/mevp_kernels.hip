@@ -85,7 +85,7 @@ __global__ void k_single_tables(DomDev D, int tx, int ty, DomDev *doms, Blk *ebl
     int start = 0;
     for (int xx = 0; xx < x; ++xx) start += (n_tiles - xx + kNumXcd - 1) / kNumXcd;
     int col, row;
-    strip_tile(start + s, ntx, nty, kStripTiles, col, row);
+    strip_tile(start + s, ntx, nty, strip_width(tx, kStripElems), col, row);
     tiles[i] = Tile{0, col * tx, row * ty, 0};
   }
 }

@@ -181,22 +181,22 @@ static void check_multi(const Domain &D, std::vector<int> &node_seen, std::vecto
 }
 
 // The strip order of a domain's tiles lists every tile of the ntx x nty grid
-// exactly once, column strips of kStripTiles left to right, rows bottom to
+// exactly once, column strips of `strip` tiles left to right, rows bottom to
 // top within a strip.
-static void check_strip_order(int ntx, int nty) {
+static void check_strip_order(int ntx, int nty, int strip) {
   std::vector<int> seen((size_t)ntx * nty, 0);
   int prev_strip = 0, prev_row = 0, prev_col = -1;
   for (int k = 0; k < ntx * nty; ++k) {
     int col, row;
-    strip_tile(k, ntx, nty, kStripTiles, col, row);
+    strip_tile(k, ntx, nty, strip, col, row);
     CHECK(col >= 0 && col < ntx && row >= 0 && row < nty, "tile %d of %dx%d -> (%d, %d)", k, ntx,
           nty, col, row);
     CHECK(seen[(size_t)row * ntx + col]++ == 0, "tile (%d, %d) listed twice", col, row);
-    const int strip = col / kStripTiles;
-    CHECK(strip > prev_strip || (strip == prev_strip && (row > prev_row ||
-                                                         (row == prev_row && col > prev_col))),
+    const int sj = col / strip;
+    CHECK(sj > prev_strip || (sj == prev_strip && (row > prev_row ||
+                                                   (row == prev_row && col > prev_col))),
           "tile %d of %dx%d out of strip order", k, ntx, nty);
-    prev_strip = strip;
+    prev_strip = sj;
     prev_row = row;
     prev_col = col;
   }
@@ -233,11 +233,18 @@ int main() {
     D.nn = D.NX * D.NY;
     for (int sh = 0; sh < kNumTileShapes; ++sh) {
       const int tx = kTileShapes[sh][0] - 1, ty = kTileShapes[sh][1] - 1;
-      check_strip_order((D.nx + tx - 1) / tx, (D.ny + ty - 1) / ty);
+      const int strip = strip_width(tx, kStripElems);
+      if (strip < 1 || strip * tx > 2 * kStripElems) {
+        fprintf(stderr, "FAIL: strip of %d tiles for tiles %d wide\n", strip, tx);
+        return 1;
+      }
+      check_strip_order((D.nx + tx - 1) / tx, (D.ny + ty - 1) / ty, strip);
     }
-    check_strip_order(65, 3);
-    check_strip_order(16, 5);
-    check_strip_order(47, 31);
+    for (int strip : {1, 3, 8, 16, 20}) {
+      check_strip_order(65, 3, strip);
+      check_strip_order(16, 5, strip);
+      check_strip_order(47, 31, strip);
+    }
     for (int K = 1; K <= 3; ++K) {
       check_shape<kTileShapes[0][0], kTileShapes[0][1]>(D, K);
       check_shape<kTileShapes[1][0], kTileShapes[1][1]>(D, K);
