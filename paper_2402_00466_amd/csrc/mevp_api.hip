@@ -588,8 +588,10 @@ static bool inputs_set(const mevp_ctx *ctx) {
 
 static mevp_status begin_step_on(mevp_ctx *ctx, hipStream_t stream) {
   const int slot = timer_start(ctx, 2);
+  int ntiles = 0;
+  for (int k = 0; k < kNumGeo; ++k) ntiles += ctx->tile_split.n[k];
   mevp_status st = hip_status(launch_begin_step(ctx->d, ctx->kp, ctx->na, ctx->ns,
-                                                v_buf(ctx, ctx->cur), ctx->n_nblk,
+                                                v_buf(ctx, ctx->cur), ctx->shape, ntiles,
                                                 stream));
   timer_stop(ctx, 2, slot);
   return st;

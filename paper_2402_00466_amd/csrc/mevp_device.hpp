@@ -1352,123 +1352,168 @@ __global__ void __launch_bounds__(EX *EY) k_fused_persist(DevArrays d, KParams p
 }
 
 // ---------------------------------------------------------------------------
-// Start of a time step: lumped masses gathered per node in ascending element
-// order from per-element integrals computed on the fly, air stress, and the
-// six node constants of the velocity update: c = M^H/dt, m^A rho_o C_o,
-// g = c v^n + m^A tau_a (2), ocean velocity (2).
+// Start of a time step, on the fused kernels' tiles: every element of the
+// tile (with its one-element low halo) integrates rho_i h and a against the
+// basis functions of its 9 CG2 nodes into LDS, then every interior node the
+// tile owns gathers its lumped masses M^H, m^A from the <= 4 elements around
+// it in ascending element order and writes the six node constants of the
+// velocity update: c = M^H/dt, m^A rho_o C_o, g = c v^n + m^A tau_a (2),
+// ocean velocity (2). Boundary nodes (Dirichlet, never updated) get zeros.
 // ---------------------------------------------------------------------------
-template <int NS, int NA>
-__global__ void __launch_bounds__(kNodeBlock) k_begin_step(DevArrays d, KParams p,
-                                                           const double *v) {
-  using Q = Quad<Ngp<NS>::value>;
-  const Blk blk = d.nblk[blockIdx.x];
-  const DomDev D = d.doms[blk.dom];
-  const int j = blk.first + (int)threadIdx.x;
-  if (j >= D.nn) return;
-  const int NX = 2 * D.nx + 1;
-  const int ix = j % NX, iy = j / NX;
-  const size_t o = 2 * (size_t)D.node_off;
 
-  // The elements around node (ix, iy): candidates ((ix-1)/2 + s, (iy-1)/2 + t),
-  // s, t in {0, 1}, in ascending element order; the second column (row) exists
-  // only for an even ix (iy), and each must lie in the domain. All four are
-  // evaluated without branches, so their loads are issued together; a missing
-  // one is evaluated on a clamped element and added as +0.0, which leaves the
-  // sum, in ascending element order, equal to the one over the elements that
-  // exist.
-  const size_t ne = (size_t)D.ne;
+// int rho_i h phi_a and int a phi_a over element (ex, ey) for its 9 local
+// nodes a = 3 b + c (phi_a = L_c(xi) L_b(eta)), with h, a clamped at the
+// Gauss points as in the stress listings
+template <int NS, int NA>
+__device__ __forceinline__ void element_masses(const DevArrays &d, const DomDev &D,
+                                               const KParams &p, int ex, int ey, double (&mh)[9],
+                                               double (&ma)[9]) {
+  using Q = Quad<Ngp<NS>::value>;
+  constexpr int NGP = Ngp<NS>::value;
+  const size_t ne = (size_t)D.ne, e = (size_t)ey * D.nx + ex;
   const double *Hd = d.H + (size_t)NA * D.elem_off;
   const double *Ad = d.A + (size_t)NA * D.elem_off;
-  constexpr int NGP = Ngp<NS>::value;
-  const int exf = (ix - 1) >> 1, eyf = (iy - 1) >> 1;
-  double sh[4], sa[4];
-  bool ok[4];
+  double Hc[NA], Ac[NA];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int s = m & 1, t = m >> 1;
-    const int ex = exf + s, ey = eyf + t;
-    ok[m] = (s == 0 || !(ix & 1)) && (t == 0 || !(iy & 1)) && ex >= 0 && ey >= 0 &&
-            ex < D.nx && ey < D.ny;
-    const int exc = min(max(ex, 0), D.nx - 1), eyc = min(max(ey, 0), D.ny - 1);
-    // local node (b, c) of the node in the element (clamped for a missing one)
-    const int bb = min(max(iy - 2 * eyc, 0), 2), cc = min(max(ix - 2 * exc, 0), 2);
-    const size_t e = (size_t)eyc * D.nx + exc;
-    double Hc[NA], Ac[NA];
+  for (int k = 0; k < NA; ++k) {
+    Hc[k] = Hd[k * ne + e];
+    Ac[k] = Ad[k * ne + e];
+  }
+  if (NA == 1 && D.kind == kGeoAffine) {
+    // parallelogram cell, constant fields: |J|, h and a are constants, and
+    // the rule integrates the product of the two quadratics L_c, L_b exactly,
+    // to the Simpson weights 1/6, 2/3, 1/6 of [0, 1]
+    const Cell<double> cell = load_cell<double>(D, d.vert, ex, ey);
+    double J00, J01, J10, J11;
+    cell.jac(0.5, 0.5, J00, J01, J10, J11);
+    const double det = J00 * J11 - J01 * J10;
+    const double h = fmax(0.0, Hc[0]), ac = fmin(1.0, fmax(0.0, Ac[0]));
 #pragma unroll
-    for (int k = 0; k < NA; ++k) {
-      Hc[k] = Hd[k * ne + e];
-      Ac[k] = Ad[k * ne + e];
+    for (int a = 0; a < 9; ++a) {
+      const double wa = (a % 3 == 1 ? 2.0 / 3.0 : 1.0 / 6.0) * (a / 3 == 1 ? 2.0 / 3.0 : 1.0 / 6.0);
+      mh[a] = wa * det * p.rho_i * h;
+      ma[a] = wa * det * ac;
     }
-    // the node's CG2 basis function at the Gauss points: L_c(x_i) L_b(x_j)
-    double Lx[NGP], Ly[NGP];
+    return;
+  }
+  auto integrals = [&](const auto &cell) {
 #pragma unroll
-    for (int i = 0; i < NGP; ++i) {
-      const double x = Gauss1D<NGP>::x[i];
-      Lx[i] = cc == 0 ? q2_1d(0, x) : (cc == 1 ? q2_1d(1, x) : q2_1d(2, x));
-      Ly[i] = bb == 0 ? q2_1d(0, x) : (bb == 1 ? q2_1d(1, x) : q2_1d(2, x));
-    }
-    // int rho_i h phi_a and int a phi_a over the element, for its cell map
-    auto integrals = [&](const auto &cell) {
-      double h_int = 0.0, a_int = 0.0;
+    for (int a = 0; a < 9; ++a) mh[a] = ma[a] = 0.0;
 #pragma unroll
-      for (int q = 0; q < Q::NG; ++q) {
-        double J00, J01, J10, J11;
-        cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
-        const double wd = Q::w(q) * (J00 * J11 - J01 * J10);
-        double hs = 0.0, as = 0.0;
-#pragma unroll
-        for (int k = 0; k < NA; ++k) {
-          hs += Hc[k] * Q::psi(k, q);
-          as += Ac[k] * Q::psi(k, q);
-        }
-        const double h = fmax(0.0, hs), ac = fmin(1.0, fmax(0.0, as));
-        const double phi = Lx[q % NGP] * Ly[q / NGP];
-        h_int += wd * p.rho_i * h * phi;
-        a_int += wd * ac * phi;
-      }
-      sh[m] = h_int;
-      sa[m] = a_int;
-    };
-    if (D.kind == kGeoIso) {
-      integrals(load_q2map<double>(D, d.xnode, exc, eyc));
-    } else if (NA == 1 && D.kind == kGeoAffine) {
-      // parallelogram cell, constant fields: |J|, h and a are constants, and
-      // the rule integrates the product of the two quadratics L_c, L_b
-      // exactly, to the Simpson weights 1/6, 2/3, 1/6 of [0, 1]
-      const Cell<double> cell = load_cell<double>(D, d.vert, exc, eyc);
+    for (int q = 0; q < Q::NG; ++q) {
       double J00, J01, J10, J11;
-      cell.jac(0.5, 0.5, J00, J01, J10, J11);
-      const double det = J00 * J11 - J01 * J10;
-      const double wa = (cc == 1 ? 2.0 / 3.0 : 1.0 / 6.0) * (bb == 1 ? 2.0 / 3.0 : 1.0 / 6.0);
-      const double h = fmax(0.0, Hc[0]), ac = fmin(1.0, fmax(0.0, Ac[0]));
-      sh[m] = wa * det * p.rho_i * h;
-      sa[m] = wa * det * ac;
-    } else {
-      integrals(load_cell<double>(D, d.vert, exc, eyc));
-    }
-  }
-  double MH = 0.0, mA = 0.0;
+      cell.jac(Q::xi(q), Q::eta(q), J00, J01, J10, J11);
+      const double wd = Q::w(q) * (J00 * J11 - J01 * J10);
+      double hs = 0.0, as = 0.0;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    MH += ok[m] ? sh[m] : 0.0;
-    mA += ok[m] ? sa[m] : 0.0;
-  }
-  const double wx = d.wind[o + j], wy = d.wind[o + D.nn + j];
-  const double sp = sqrt(wx * wx + wy * wy);
-  const double c = MH * p.inv_dt;
-  double *nc = d.nc + (size_t)6 * D.node_off;
-  const size_t nn = (size_t)D.nn;
-  nc[j] = c;
-  nc[nn + j] = mA * p.rhoCo;
-  nc[2 * nn + j] = c * v[o + j] + mA * (p.rhoCa * sp * wx);
-  nc[3 * nn + j] = c * v[o + D.nn + j] + mA * (p.rhoCa * sp * wy);
-  nc[4 * nn + j] = d.ocean[o + j];
-  nc[5 * nn + j] = d.ocean[o + D.nn + j];
+      for (int k = 0; k < NA; ++k) {
+        hs += Hc[k] * Q::psi(k, q);
+        as += Ac[k] * Q::psi(k, q);
+      }
+      const double h = fmax(0.0, hs), ac = fmin(1.0, fmax(0.0, as));
+      const double x = Gauss1D<NGP>::x[q % NGP], y = Gauss1D<NGP>::x[q / NGP];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        const double phi = q2_1d(a % 3, x) * q2_1d(a / 3, y);
+        mh[a] += wd * p.rho_i * h * phi;
+        ma[a] += wd * ac * phi;
+      }
+    }
+  };
+  if (D.kind == kGeoIso)
+    integrals(load_q2map<double>(D, d.xnode, ex, ey));
+  else
+    integrals(load_cell<double>(D, d.vert, ex, ey));
 }
 
-// Per domain: 1 if every cell is a parallelogram (its edge vectors agree
-// exactly in double), 0 otherwise. The flag starts at 1; any lane that finds
-// a general cell stores 0.
+template <int NS, int NA, int EX, int EY>
+__global__ void __launch_bounds__(EX *EY) k_begin_tile(DevArrays d, KParams p, const Tile *tiles,
+                                                        const double *v) {
+  constexpr int TX = EX - 1, TY = EY - 1, NT = EX * EY;
+  constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;  // node rounds per lane
+  __shared__ double fl[18][NT];  // the elements' nodal integrals: rho_i h (0..8), a (9..17)
+  const Tile t = tiles[blockIdx.x];
+  const DomDev D = d.doms[t.dom];
+  const int tid = (int)threadIdx.x;
+  {
+    const int ex = t.x0 - 1 + tid % EX, ey = t.y0 - 1 + tid / EX;
+    if (ex >= 0 && ey >= 0 && ex < D.nx && ey < D.ny) {
+      double mh[9], ma[9];
+      element_masses<NS, NA>(d, D, p, ex, ey, mh, ma);
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        fl[a][tid] = mh[a];
+        fl[9 + a][tid] = ma[a];
+      }
+    }
+  }
+  // the owned nodes, up to R per lane: index them and issue their loads
+  // (wind, ocean, v^n) before the barrier, as they do not depend on it
+  const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
+  const size_t nn = (size_t)D.nn, o = 2 * (size_t)D.node_off;
+  const NodeRange own = owned_nodes(t.x0, t.y0, TX, TY, D.nx, D.ny, NX, NY);
+  const int w = own.ix1 - own.ix0, n = w * (own.iy1 - own.iy0);
+  static_assert(R * NT <= 8192, "node rounds beyond the exact float division");
+  const float rw = 1.0f / (float)w;
+  int ixs[R], iys[R];
+  bool act[R], bnd[R];
+  double in[R][6];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int k = tid + m * NT;
+    act[m] = k < n;
+    int dx, dy;
+    node_in_range(act[m] ? k : 0, w, rw, dx, dy);
+    ixs[m] = own.ix0 + dx;
+    iys[m] = own.iy0 + dy;
+    bnd[m] = ixs[m] == 0 || iys[m] == 0 || ixs[m] == NX - 1 || iys[m] == NY - 1;
+    if (act[m] && !bnd[m]) {
+      const size_t j = (size_t)iys[m] * NX + ixs[m];
+      in[m][0] = d.wind[o + j];
+      in[m][1] = d.wind[o + nn + j];
+      in[m][2] = d.ocean[o + j];
+      in[m][3] = d.ocean[o + nn + j];
+      in[m][4] = v[o + j];
+      in[m][5] = v[o + nn + j];
+    }
+  }
+  __syncthreads();
+  double *nc = d.nc + (size_t)6 * D.node_off;
+  const double *f = &fl[0][0];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    if (!act[m]) continue;
+    const int ix = ixs[m], iy = iys[m];
+    const size_t j = (size_t)iy * NX + ix;
+    if (bnd[m]) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) nc[c * nn + j] = 0.0;
+      continue;
+    }
+    // the <= 4 elements around the node, in ascending element order (the
+    // force table's layout; a missing element adds +0.0)
+    int off[4];
+    bool two_x, two_y;
+    node_force_offsets(ix, iy, t.x0 - 1, t.y0 - 1, EX, NT, off, two_x, two_y);
+    double MH = 0.0 + f[off[0]], mA = 0.0 + f[9 * NT + off[0]];
+    MH += two_x ? f[off[1]] : 0.0;
+    mA += two_x ? f[9 * NT + off[1]] : 0.0;
+    MH += two_y ? f[off[2]] : 0.0;
+    mA += two_y ? f[9 * NT + off[2]] : 0.0;
+    MH += (two_x && two_y) ? f[off[3]] : 0.0;
+    mA += (two_x && two_y) ? f[9 * NT + off[3]] : 0.0;
+    const double wx = in[m][0], wy = in[m][1];
+    const double sp = sqrt(wx * wx + wy * wy);
+    const double c = MH * p.inv_dt;
+    nc[j] = c;
+    nc[nn + j] = mA * p.rhoCo;
+    nc[2 * nn + j] = c * in[m][4] + mA * (p.rhoCa * sp * wx);
+    nc[3 * nn + j] = c * in[m][5] + mA * (p.rhoCa * sp * wy);
+    nc[4 * nn + j] = in[m][2];
+    nc[5 * nn + j] = in[m][3];
+  }
+}
+
 __global__ void __launch_bounds__(kElemBlock) k_cell_shape(DevArrays d, int dom, int *flag) {
   const DomDev D = d.doms[dom];
   for (int el = blockIdx.x * blockDim.x + threadIdx.x; el < D.ne; el += gridDim.x * blockDim.x) {
@@ -1713,10 +1758,19 @@ __device__ __forceinline__ void advect_element(const DevArrays &d, const DomDev 
 // Launch helpers
 // ---------------------------------------------------------------------------
 template <int NS, int NA>
-inline hipError_t begin_step_t(const DevArrays &d, const KParams &p, const double *v, int n_nblk,
-                               hipStream_t s) {
-  hipLaunchKernelGGL((k_begin_step<NS, NA>), dim3(n_nblk), dim3(kNodeBlock), 0, s, d, p, v);
-  return hipGetLastError();
+inline hipError_t begin_step_t(const DevArrays &d, const KParams &p, const double *v, int shape,
+                               int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+#define MEVP_BT(SH_)                                                                          \
+  if (shape == SH_) {                                                                         \
+    constexpr int EX = kTileShapes[SH_][0], EY = kTileShapes[SH_][1];                          \
+    hipLaunchKernelGGL((k_begin_tile<NS, NA, EX, EY>), dim3(ntiles), dim3(EX * EY), 0, s, d, p, \
+                       d.tiles, v);                                                          \
+    return hipGetLastError();                                                                 \
+  }
+  MEVP_BT(0) MEVP_BT(1) MEVP_BT(2) MEVP_BT(3)
+#undef MEVP_BT
+  return hipErrorInvalidValue;
 }
 
 // Two-phase subcycle: element kernel(s) per geometry kind, then the node kernel.
@@ -1839,10 +1893,11 @@ inline hipError_t fused_t(const DevArrays &d, const KParams &p, const Launch &L,
 // unit instantiates them for its n_s.
 template <int NS>
 inline hipError_t begin_step_ns(const DevArrays &d, const KParams &p, int n_a, const double *v,
-                                int n_nblk, hipStream_t s) {
-  if (n_a == 1) return begin_step_t<NS, 1>(d, p, v, n_nblk, s);
-  if (n_a == 3) return begin_step_t<NS, 3>(d, p, v, n_nblk, s);
-  if (n_a == 6) return begin_step_t<NS, 6>(d, p, v, n_nblk, s);
+                                int shape, int ntiles, hipStream_t s) {
+  static_assert(kNumTileShapes == 4, "begin_step_t dispatches on the four tile shapes");
+  if (n_a == 1) return begin_step_t<NS, 1>(d, p, v, shape, ntiles, s);
+  if (n_a == 3) return begin_step_t<NS, 3>(d, p, v, shape, ntiles, s);
+  if (n_a == 6) return begin_step_t<NS, 6>(d, p, v, shape, ntiles, s);
   return hipErrorInvalidValue;
 }
 

@@ -114,8 +114,10 @@ constexpr int kNumXcd = 8;
 constexpr int kStripElems = 256;
 
 // Launchers (mevp_kernels.hip). Return hipSuccess or the launch error.
+// start of a time step on the ntiles fused-kernel tiles of tile shape `shape`
+// (d.tiles: every tile of every domain)
 hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int n_s,
-                             const double *v, int n_nblk, hipStream_t s);
+                             const double *v, int shape, int ntiles, hipStream_t s);
 // prec: a mevp_precision (0 FP64, 1 mixed, 2 mixed with bfloat16 element
 // matrices, fused kernels at n_s = 6 and n_a = 1 only)
 hipError_t launch_element_phase(const DevArrays &d, const KParams &p, int n_s, int n_a,
@@ -147,9 +149,12 @@ template <int NS, int NA, class T, int EX, int EY>
 hipError_t fused_affine(const DevArrays &d, const KParams &p, const Tile *tiles, int ntiles,
                         const FusedArgs &f, hipStream_t s);
 // per-n_s launchers (mevp_kernels_ns{3,6,8}.hip)
-hipError_t begin_step_ns3(const DevArrays &, const KParams &, int, const double *, int, hipStream_t);
-hipError_t begin_step_ns6(const DevArrays &, const KParams &, int, const double *, int, hipStream_t);
-hipError_t begin_step_ns8(const DevArrays &, const KParams &, int, const double *, int, hipStream_t);
+hipError_t begin_step_ns3(const DevArrays &, const KParams &, int, const double *, int, int,
+                          hipStream_t);
+hipError_t begin_step_ns6(const DevArrays &, const KParams &, int, const double *, int, int,
+                          hipStream_t);
+hipError_t begin_step_ns8(const DevArrays &, const KParams &, int, const double *, int, int,
+                          hipStream_t);
 hipError_t two_phase_ns3(const DevArrays &, const KParams &, int, bool, const Launch &, Bufs, hipStream_t);
 hipError_t two_phase_ns6(const DevArrays &, const KParams &, int, bool, const Launch &, Bufs, hipStream_t);
 hipError_t two_phase_ns8(const DevArrays &, const KParams &, int, bool, const Launch &, Bufs, hipStream_t);

@@ -104,10 +104,10 @@ inline unsigned grid_for(size_t n, unsigned block) {
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_begin_step(const DevArrays &d, const KParams &p, int n_a, int n_s,
-                             const double *v, int n_nblk, hipStream_t s) {
-  if (n_s == 3) return begin_step_ns3(d, p, n_a, v, n_nblk, s);
-  if (n_s == 6) return begin_step_ns6(d, p, n_a, v, n_nblk, s);
-  if (n_s == 8) return begin_step_ns8(d, p, n_a, v, n_nblk, s);
+                             const double *v, int shape, int ntiles, hipStream_t s) {
+  if (n_s == 3) return begin_step_ns3(d, p, n_a, v, shape, ntiles, s);
+  if (n_s == 6) return begin_step_ns6(d, p, n_a, v, shape, ntiles, s);
+  if (n_s == 8) return begin_step_ns8(d, p, n_a, v, shape, ntiles, s);
   return hipErrorInvalidValue;
 }
 

@@ -5,8 +5,8 @@
 namespace mevp {
 
 hipError_t begin_step_ns6(const DevArrays &d, const KParams &p, int n_a, const double *v,
-                          int n_nblk, hipStream_t s) {
-  return begin_step_ns<6>(d, p, n_a, v, n_nblk, s);
+                          int shape, int ntiles, hipStream_t s) {
+  return begin_step_ns<6>(d, p, n_a, v, shape, ntiles, s);
 }
 
 hipError_t two_phase_ns6(const DevArrays &d, const KParams &p, int n_a, bool mixed,
