@@ -921,15 +921,18 @@ __device__ __forceinline__ void element_update(const DevArrays &d, const DomDev 
 // Velocity update of one interior node:
 //   (c (1+beta) + d) v + b k x v = c beta v^{p-1} + g + d v_o + F
 // with c = M^H/dt, b = f M^H, d = m^A rho_o C_o |v_o - v^{p-1}| and
-// g = c v^n + m^A tau_a (node constants nc[6][nn] of the step), closed form.
+// g = c v^n + m^A tau_a, closed form. The node constants of the step are
+// interleaved per node, nc[nn][6] = {c, m^A rho_o C_o, g_x, g_y, v_o,x, v_o,y}
+// (48 bytes a node: three 16-byte loads).
 __device__ __forceinline__ void velocity_update6(const KParams &p, const double (&o)[6], double ux,
                                                  double uy, double Fx, double Fy, double &vx,
                                                  double &vy);
-__device__ __forceinline__ void velocity_update(const KParams &p, const double *nc, size_t nn,
-                                                int j, double ux, double uy, double Fx,
-                                                double Fy, double &vx, double &vy) {
-  const double o[6] = {nc[j], nc[nn + j], nc[2 * nn + j], nc[3 * nn + j], nc[4 * nn + j],
-                       nc[5 * nn + j]};
+__device__ __forceinline__ void velocity_update(const KParams &p, const double *nc, int j,
+                                                double ux, double uy, double Fx, double Fy,
+                                                double &vx, double &vy) {
+  const double2 *r = reinterpret_cast<const double2 *>(nc + 6 * (size_t)j);
+  const double2 a = r[0], b = r[1], c = r[2];
+  const double o[6] = {a.x, a.y, b.x, b.y, c.x, c.y};
   velocity_update6(p, o, ux, uy, Fx, Fy, vx, vy);
 }
 
@@ -1020,8 +1023,7 @@ __global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p, Buf
     }
   }
   double vx, vy;
-  velocity_update(p, d.nc + (size_t)6 * D.node_off, (size_t)D.nn, j, vin[j], vin[D.nn + j], Fx,
-                  Fy, vx, vy);
+  velocity_update(p, d.nc + (size_t)6 * D.node_off, j, vin[j], vin[D.nn + j], Fx, Fy, vx, vy);
   vout[j] = vx;
   vout[D.nn + j] = vy;
 }
@@ -1050,7 +1052,6 @@ struct NodeBatch {
                                        int iy0, int iy1, UIn uin) {
     const int tid = (int)threadIdx.x;
     const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
-    const size_t nn = (size_t)D.nn;
     const int w = ix1 - ix0, n = w * (iy1 - iy0);
     static_assert(R * NT <= 8192, "node rounds beyond the exact float division");
     const float rw = 1.0f / (float)w;
@@ -1066,8 +1067,14 @@ struct NodeBatch {
       bnd[m] = ixs[m] == 0 || iys[m] == 0 || ixs[m] == NX - 1 || iys[m] == NY - 1;
       if (act[m] && !bnd[m]) {
         uin(ixs[m], iys[m], jn[m], ux[m], uy[m]);
+        // the node's six constants, interleaved: three 16-byte loads
+        const double2 *r = reinterpret_cast<const double2 *>(nc + 6 * (size_t)jn[m]);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) o[m][c] = nc[c * nn + jn[m]];
+        for (int c = 0; c < 3; ++c) {
+          const double2 t = r[c];
+          o[m][2 * c] = t.x;
+          o[m][2 * c + 1] = t.y;
+        }
       }
     }
   }
@@ -1487,7 +1494,7 @@ __global__ void __launch_bounds__(EX *EY) k_begin_tile(DevArrays d, KParams p, c
     const size_t j = (size_t)iy * NX + ix;
     if (bnd[m]) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) nc[c * nn + j] = 0.0;
+      for (int c = 0; c < 6; ++c) nc[6 * j + c] = 0.0;
       continue;
     }
     // the <= 4 elements around the node, in ascending element order (the
@@ -1505,12 +1512,11 @@ __global__ void __launch_bounds__(EX *EY) k_begin_tile(DevArrays d, KParams p, c
     const double wx = in[m][0], wy = in[m][1];
     const double sp = sqrt(wx * wx + wy * wy);
     const double c = MH * p.inv_dt;
-    nc[j] = c;
-    nc[nn + j] = mA * p.rhoCo;
-    nc[2 * nn + j] = c * in[m][4] + mA * (p.rhoCa * sp * wx);
-    nc[3 * nn + j] = c * in[m][5] + mA * (p.rhoCa * sp * wy);
-    nc[4 * nn + j] = in[m][2];
-    nc[5 * nn + j] = in[m][3];
+    // interleaved per node (see velocity_update)
+    double2 *r = reinterpret_cast<double2 *>(nc + 6 * j);
+    r[0] = double2{c, mA * p.rhoCo};
+    r[1] = double2{c * in[m][4] + mA * (p.rhoCa * sp * wx), c * in[m][5] + mA * (p.rhoCa * sp * wy)};
+    r[2] = double2{in[m][2], in[m][3]};
   }
 }
 

@@ -85,7 +85,7 @@ struct DevArrays {
   const double *wind;  // [dom][2][nn]
   const double *ocean;
   double *v;           // [dom][2][nn] (two buffers: v and v + 2 * total nodes)
-  double *nc;          // [dom][6][nn] node constants of the velocity update
+  double *nc;          // [dom][nn][6] node constants of the velocity update, per node
   void *S;             // [dom][3][n_s][ne], double or float (two buffers)
   void *fe;            // [dom][18][ne] element nodal forces, double or float
   int *flag;           // check results
