@@ -548,8 +548,14 @@ mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const dou
       return MEVP_EINVAL;  // the rounding to float runs on the device: S must be device memory
     }
   }
-  mevp_status st = copy(v_buf(ctx, ctx->cur) + 2 * (size_t)D.node_off, v_xy,
-                        sizeof(double) * 2 * D.nn, ctx->stream);
+  // v_xy (host or device, [2][nn]) to the other state buffer, then interleaved
+  // per node ([nn][2]) into the current one: the other buffer is free until
+  // the next subcycle writes it
+  const size_t vo = 2 * (size_t)D.node_off;
+  mevp_status st = copy(v_buf(ctx, ctx->cur ^ 1) + vo, v_xy, sizeof(double) * 2 * D.nn, ctx->stream);
+  if (st == MEVP_OK)
+    st = hip_status(launch_interleave2(v_buf(ctx, ctx->cur ^ 1) + vo, v_buf(ctx, ctx->cur) + vo,
+                                       (size_t)D.nn, ctx->stream));
   if (st != MEVP_OK) return st;
   if (ctx->prec == MEVP_FP64)
     return copy(static_cast<double *>(S_buf(ctx, ctx->cur)) + o, S, sizeof(double) * n, ctx->stream);
@@ -567,8 +573,14 @@ mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S) {
     }
   }
   if (v_xy) {
-    mevp_status st = copy(v_xy, v_buf(ctx, ctx->cur) + 2 * (size_t)D.node_off,
-                          sizeof(double) * 2 * D.nn, ctx->stream);
+    // back to [2][nn] through the other state buffer (free until the next
+    // subcycle), then to v_xy (host or device)
+    const size_t vo = 2 * (size_t)D.node_off;
+    mevp_status st = hip_status(launch_deinterleave2(v_buf(ctx, ctx->cur) + vo,
+                                                     v_buf(ctx, ctx->cur ^ 1) + vo, (size_t)D.nn,
+                                                     ctx->stream));
+    if (st == MEVP_OK)
+      st = copy(v_xy, v_buf(ctx, ctx->cur ^ 1) + vo, sizeof(double) * 2 * D.nn, ctx->stream);
     if (st != MEVP_OK) return st;
   }
   if (S) {
@@ -1283,7 +1295,7 @@ mevp_status step_static_impl(const mevp_params *params, mevp_precision precision
                                        L.n_tiles, s));
   // state in, the step, state out
   const size_t nS = (size_t)3 * c.ns * D.ne;
-  if (st == MEVP_OK) st = copy(v_buf(&c, 0), v_xy, sizeof(double) * 2 * D.nn, s);
+  if (st == MEVP_OK) st = hip_status(launch_interleave2(v_xy, v_buf(&c, 0), (size_t)D.nn, s));
   if (st == MEVP_OK) {
     if (precision == MEVP_FP64)
       st = copy(S_buf(&c, 0), S, sizeof(double) * nS, s);
@@ -1292,7 +1304,7 @@ mevp_status step_static_impl(const mevp_params *params, mevp_precision precision
   }
   if (st == MEVP_OK) st = begin_step_on(&c, s);
   if (st == MEVP_OK) st = subcycles_on(&c, n_subcycles, s);
-  if (st == MEVP_OK) st = copy(v_xy, v_buf(&c, c.cur), sizeof(double) * 2 * D.nn, s);
+  if (st == MEVP_OK) st = hip_status(launch_deinterleave2(v_buf(&c, c.cur), v_xy, (size_t)D.nn, s));
   if (st == MEVP_OK) {
     if (precision == MEVP_FP64)
       st = copy(S, S_buf(&c, c.cur), sizeof(double) * nS, s);

@@ -343,13 +343,28 @@ __device__ __forceinline__ void gather_velocity(const double *vxs, const double 
     }
 }
 
-// the same for element (ex, ey) of a domain, from the global v array
+// the same for element (ex, ey) of a domain, from the global v array, whose
+// velocities are interleaved per node (v[nn][2]: one 16-byte load a node)
 template <class T>
 __device__ __forceinline__ void load_velocity(const DomDev &D, const double *v, int ex, int ey,
                                               T (&vx)[9], T (&vy)[9]) {
-  const double *vxg = v + 2 * (size_t)D.node_off;
-  const int NX = 2 * D.nx + 1;
-  gather_velocity<T>(vxg, vxg + D.nn, 2 * ey * NX + 2 * ex, NX, vx, vy);
+  const double2 *V = reinterpret_cast<const double2 *>(v + 2 * (size_t)D.node_off);
+  const int NX = 2 * D.nx + 1, j0 = 2 * ey * NX + 2 * ex;
+  double2 u[9];
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[3 * b + c] = V[j0 + b * NX + c];
+  double bx = 0.0, by = 0.0;
+  if (sizeof(T) < sizeof(double)) {
+    bx = u[0].x;
+    by = u[0].y;
+  }
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    vx[a] = T(u[a].x - bx);
+    vy[a] = T(u[a].y - by);
+  }
 }
 
 // Isoparametric cell map: x(xi, eta) = sum_a X_a phi_a(xi, eta) over the 9
@@ -999,8 +1014,7 @@ __global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p, Buf
   const double *vin = b.v_in + 2 * (size_t)D.node_off;
   double *vout = b.v_out + 2 * (size_t)D.node_off;
   if (ix == 0 || iy == 0 || ix == NX - 1 || iy == NY - 1) {
-    vout[j] = 0.0;
-    vout[D.nn + j] = 0.0;
+    reinterpret_cast<double2 *>(vout)[j] = double2{0.0, 0.0};
     return;
   }
   // elements around node (ix, iy): for an odd index the one element whose
@@ -1023,9 +1037,9 @@ __global__ void __launch_bounds__(kNodeBlock) k_node(DevArrays d, KParams p, Buf
     }
   }
   double vx, vy;
-  velocity_update(p, d.nc + (size_t)6 * D.node_off, j, vin[j], vin[D.nn + j], Fx, Fy, vx, vy);
-  vout[j] = vx;
-  vout[D.nn + j] = vy;
+  const double2 u = reinterpret_cast<const double2 *>(vin)[j];
+  velocity_update(p, d.nc + (size_t)6 * D.node_off, j, u.x, u.y, Fx, Fy, vx, vy);
+  reinterpret_cast<double2 *>(vout)[j] = double2{vx, vy};
 }
 
 // ---------------------------------------------------------------------------
@@ -1158,17 +1172,16 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
   }
   // ---- nodes owned by the tile: loads before the barrier, update after ----
   const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
-  const size_t nn = (size_t)D.nn;
   const NodeRange own = owned_nodes(t.x0, t.y0, TX, TY, D.nx, D.ny, NX, NY);
   const int ix0 = own.ix0, ix1 = own.ix1, iy0 = own.iy0, iy1 = own.iy1;
   constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;
   auto uin = [&](int, int, int j, double &ux, double &uy) {
-    ux = B.v_in[j];
-    uy = B.v_in[nn + j];
+    const double2 u = reinterpret_cast<const double2 *>(B.v_in)[j];
+    ux = u.x;
+    uy = u.y;
   };
   auto out = [&](int, int, int j, double vx, double vy) {
-    B.v_out[j] = vx;
-    B.v_out[nn + j] = vy;
+    reinterpret_cast<double2 *>(B.v_out)[j] = double2{vx, vy};
   };
   NodeBatch<R, NT> nb;
   nb.load(D, d.nc + (size_t)6 * D.node_off, ix0, ix1, iy0, iy1, uin);
@@ -1213,7 +1226,7 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
   const DomBufs<TS> B(b, D, NS);
   const int tid = (int)threadIdx.x;
   const int NX = 2 * D.nx + 1, NY = 2 * D.ny + 1;
-  const size_t nn = (size_t)D.nn, ne = (size_t)D.ne;
+  const size_t ne = (size_t)D.ne;
   const double *nc = d.nc + (size_t)6 * D.node_off;
   const int ex0 = t.x0 - K, ey0 = t.y0 - K;  // element of lane (0, 0)
   const int jx0 = 2 * (ex0 + 1), jy0 = 2 * (ey0 + 1);  // node of LDS entry (0, 0)
@@ -1284,8 +1297,9 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
       };
       if (i == 0) {
         auto uin = [&](int, int, int j, double &ux, double &uy) {
-          ux = B.v_in[j];
-          uy = B.v_in[nn + j];
+          const double2 u = reinterpret_cast<const double2 *>(B.v_in)[j];
+          ux = u.x;
+          uy = u.y;
         };
         NodeBatch<R, NT> nb;
         nb.load(D, nc, ix0, ix1, iy0, iy1, uin);
@@ -1313,8 +1327,7 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
         uy = vl[1][q];
       };
       auto out = [&](int, int, int j, double vx, double vy) {
-        B.v_out[j] = vx;
-        B.v_out[nn + j] = vy;
+        reinterpret_cast<double2 *>(B.v_out)[j] = double2{vx, vy};
       };
       NodeBatch<R, NT> nb;
       nb.load(D, nc, ix0, ix1, iy0, iy1, uin);
@@ -1480,8 +1493,9 @@ __global__ void __launch_bounds__(EX *EY) k_begin_tile(DevArrays d, KParams p, c
       in[m][1] = d.wind[o + nn + j];
       in[m][2] = d.ocean[o + j];
       in[m][3] = d.ocean[o + nn + j];
-      in[m][4] = v[o + j];
-      in[m][5] = v[o + nn + j];
+      const double2 u = reinterpret_cast<const double2 *>(v + o)[j];
+      in[m][4] = u.x;
+      in[m][5] = u.y;
     }
   }
   __syncthreads();

@@ -84,7 +84,7 @@ struct DevArrays {
   double *adv;         // advection stages: [4][dom][n_a][ne] (H1, A1, H2, A2)
   const double *wind;  // [dom][2][nn]
   const double *ocean;
-  double *v;           // [dom][2][nn] (two buffers: v and v + 2 * total nodes)
+  double *v;           // [dom][nn][2], interleaved per node (two buffers: v and v + 2 * total nodes)
   double *nc;          // [dom][nn][6] node constants of the velocity update, per node
   void *S;             // [dom][3][n_s][ne], double or float (two buffers)
   void *fe;            // [dom][18][ne] element nodal forces, double or float
@@ -164,6 +164,9 @@ hipError_t fused_ns8(const DevArrays &, const KParams &, int, bool, const Launch
 // the bfloat16 element-matrix trial (mevp_kernels_bf16.hip)
 hipError_t fused_bf16(const DevArrays &, const KParams &, int n_s, int n_a, const Launch &,
                       const FusedArgs &, hipStream_t);
+// velocities between the public layout [2][n] and the kernels' [n][2]
+hipError_t launch_interleave2(const double *src, double *dst, size_t n, hipStream_t s);
+hipError_t launch_deinterleave2(const double *src, double *dst, size_t n, hipStream_t s);
 hipError_t launch_convert_d2f(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_convert_f2d(const float *src, double *dst, size_t n, hipStream_t s);
 hipError_t launch_check_finite(const double *p, size_t n, int *flag, int bit, hipStream_t s);

@@ -18,6 +18,20 @@ __global__ void k_d2f(const double *src, float *dst, size_t n) {
        i += (size_t)gridDim.x * blockDim.x)
     dst[i] = (float)src[i];
 }
+// [2][n] <-> [n][2] (the velocities' public and internal layouts)
+__global__ void k_interleave2(const double *src, double *dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    reinterpret_cast<double2 *>(dst)[i] = double2{src[i], src[n + i]};
+}
+__global__ void k_deinterleave2(const double *src, double *dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const double2 u = reinterpret_cast<const double2 *>(src)[i];
+    dst[i] = u.x;
+    dst[n + i] = u.y;
+  }
+}
 __global__ void k_f2d(const float *src, double *dst, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -183,6 +197,16 @@ hipError_t launch_single_tables(const DomDev &D, int tx, int ty, DomDev *doms, B
   if (n_tiles > most) most = n_tiles;
   hipLaunchKernelGGL(k_single_tables, dim3(grid_for((size_t)most, 256)), dim3(256), 0, s, D, tx, ty,
                      doms, eblk, n_eblk, nblk, n_nblk, tiles, n_tiles);
+  return hipGetLastError();
+}
+hipError_t launch_interleave2(const double *src, double *dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_interleave2, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_deinterleave2(const double *src, double *dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_deinterleave2, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 hipError_t launch_convert_d2f(const double *src, float *dst, size_t n, hipStream_t s) {
