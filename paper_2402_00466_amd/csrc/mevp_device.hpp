@@ -322,25 +322,27 @@ __device__ __forceinline__ void vp_stress(const KParams &p, double P, T A, T B, 
 }
 
 // Velocities of the 9 local nodes of an element whose first node is j0 in
-// arrays vxs, vys of row stride `stride` (global memory or LDS). In float
+// the LDS table vs of row stride `stride` (interleaved per node). In float
 // they are taken relative to local node 0 before narrowing (the gradient of a
 // constant is zero), which keeps the strain free of cancellation.
 template <class T>
-__device__ __forceinline__ void gather_velocity(const double *vxs, const double *vys, int j0,
-                                                int stride, T (&vx)[9], T (&vy)[9]) {
-  double bx = 0.0, by = 0.0;
-  if (sizeof(T) < sizeof(double)) {
-    bx = vxs[j0];
-    by = vys[j0];
-  }
+__device__ __forceinline__ void gather_velocity(const double2 *vs, int j0, int stride, T (&vx)[9],
+                                                T (&vy)[9]) {
+  double2 u[9];
 #pragma unroll
   for (int b = 0; b < 3; ++b)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int j = j0 + b * stride + c;
-      vx[3 * b + c] = T(vxs[j] - bx);
-      vy[3 * b + c] = T(vys[j] - by);
-    }
+    for (int c = 0; c < 3; ++c) u[3 * b + c] = vs[j0 + b * stride + c];
+  double bx = 0.0, by = 0.0;
+  if (sizeof(T) < sizeof(double)) {
+    bx = u[0].x;
+    by = u[0].y;
+  }
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    vx[a] = T(u[a].x - bx);
+    vy[a] = T(u[a].y - by);
+  }
 }
 
 // the same for element (ex, ey) of a domain, from the global v array, whose
@@ -1220,7 +1222,7 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
   // waves per SIMD and would spill
   constexpr bool kEarly = (NT + 63) / 64 <= 8;
   __shared__ T fl[18][NT];
-  __shared__ double vl[2][VW * VH];
+  __shared__ double2 vl[VW * VH];  // velocities, interleaved per node
   const Tile t = tiles[blockIdx.x];
   const DomDev D = d.doms[t.dom];
   const DomBufs<TS> B(b, D, NS);
@@ -1259,7 +1261,7 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
           element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
         }
       } else {
-        gather_velocity<T>(vl[0], vl[1], vlds(2 * ex, 2 * ey), VW, vx, vy);
+        gather_velocity<T>(vl, vlds(2 * ex, 2 * ey), VW, vx, vy);
         auto sold = [&](int c, int k) { return c == 0 ? S11[k] : c == 1 ? S12[k] : S22[k]; };
         if constexpr (GK == kGeoBilinear)
           element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy,
@@ -1292,8 +1294,7 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
       constexpr int R = (VW * VH + NT - 1) / NT;
       auto out = [&](int ix, int iy, int, double vx, double vy) {
         const int q = vlds(ix, iy);
-        vl[0][q] = vx;
-        vl[1][q] = vy;
+        vl[q] = double2{vx, vy};
       };
       if (i == 0) {
         auto uin = [&](int, int, int j, double &ux, double &uy) {
@@ -1308,8 +1309,9 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
       } else {
         auto uin = [&](int ix, int iy, int, double &ux, double &uy) {
           const int q = vlds(ix, iy);
-          ux = vl[0][q];
-          uy = vl[1][q];
+          const double2 u = vl[q];
+          ux = u.x;
+          uy = u.y;
         };
         NodeBatch<R, NT> nb;
         nb.load(D, nc, ix0, ix1, iy0, iy1, uin);
@@ -1323,8 +1325,9 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
       constexpr int R = ((2 * EX - 1) * (2 * EY - 1) + NT - 1) / NT;
       auto uin = [&](int ix, int iy, int, double &ux, double &uy) {
         const int q = vlds(ix, iy);
-        ux = vl[0][q];
-        uy = vl[1][q];
+        const double2 u = vl[q];
+        ux = u.x;
+        uy = u.y;
       };
       auto out = [&](int, int, int j, double vx, double vy) {
         reinterpret_cast<double2 *>(B.v_out)[j] = double2{vx, vy};
