@@ -557,9 +557,19 @@ mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const dou
     st = hip_status(launch_interleave2(v_buf(ctx, ctx->cur ^ 1) + vo, v_buf(ctx, ctx->cur) + vo,
                                        (size_t)D.nn, ctx->stream));
   if (st != MEVP_OK) return st;
-  if (ctx->prec == MEVP_FP64)
-    return copy(static_cast<double *>(S_buf(ctx, ctx->cur)) + o, S, sizeof(double) * n, ctx->stream);
-  return hip_status(launch_convert_d2f(S, static_cast<float *>(S_buf(ctx, ctx->cur)) + o, n, ctx->stream));
+  // S to the kernels' [3][ne][n_s]: in FP64 through the other state buffer (S
+  // may be host memory), in the mixed forms straight from S (device memory)
+  const size_t ne = (size_t)D.ne;
+  if (ctx->prec == MEVP_FP64) {
+    double *stage = static_cast<double *>(S_buf(ctx, ctx->cur ^ 1)) + o;
+    st = copy(stage, S, sizeof(double) * n, ctx->stream);
+    if (st == MEVP_OK)
+      st = hip_status(launch_stress_in(stage, static_cast<double *>(S_buf(ctx, ctx->cur)) + o,
+                                       false, ne, ctx->ns, ctx->stream));
+    return st;
+  }
+  return hip_status(launch_stress_in(S, static_cast<float *>(S_buf(ctx, ctx->cur)) + o, true, ne,
+                                     ctx->ns, ctx->stream));
 }
 
 mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S) {
@@ -584,10 +594,19 @@ mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S) {
     if (st != MEVP_OK) return st;
   }
   if (S) {
+    // back to [3][n_s][ne]: in FP64 through the other state buffer, then to S
+    // (host or device); in the mixed forms straight into S (device memory)
     const size_t n = (size_t)3 * ctx->ns * D.ne, o = (size_t)3 * ctx->ns * D.elem_off;
-    if (ctx->prec == MEVP_FP64)
-      return copy(S, static_cast<const double *>(S_buf(ctx, ctx->cur)) + o, sizeof(double) * n, ctx->stream);
-    return hip_status(launch_convert_f2d(static_cast<const float *>(S_buf(ctx, ctx->cur)) + o, S, n, ctx->stream));
+    const size_t ne = (size_t)D.ne;
+    if (ctx->prec == MEVP_FP64) {
+      double *stage = static_cast<double *>(S_buf(ctx, ctx->cur ^ 1)) + o;
+      mevp_status st = hip_status(launch_stress_out(static_cast<const double *>(S_buf(ctx, ctx->cur)) + o,
+                                                    false, stage, ne, ctx->ns, ctx->stream));
+      if (st == MEVP_OK) st = copy(S, stage, sizeof(double) * n, ctx->stream);
+      return st;
+    }
+    return hip_status(launch_stress_out(static_cast<const float *>(S_buf(ctx, ctx->cur)) + o, true,
+                                        S, ne, ctx->ns, ctx->stream));
   }
   return MEVP_OK;
 }
@@ -1294,23 +1313,14 @@ mevp_status step_static_impl(const mevp_params *params, mevp_precision precision
   st = hip_status(launch_single_tables(D, tx, ty, doms, eblk, L.n_eblk, nblk, L.n_nblk, tiles,
                                        L.n_tiles, s));
   // state in, the step, state out
-  const size_t nS = (size_t)3 * c.ns * D.ne;
   if (st == MEVP_OK) st = hip_status(launch_interleave2(v_xy, v_buf(&c, 0), (size_t)D.nn, s));
-  if (st == MEVP_OK) {
-    if (precision == MEVP_FP64)
-      st = copy(S_buf(&c, 0), S, sizeof(double) * nS, s);
-    else
-      st = hip_status(launch_convert_d2f(S, static_cast<float *>(S_buf(&c, 0)), nS, s));
-  }
+  if (st == MEVP_OK)
+    st = hip_status(launch_stress_in(S, S_buf(&c, 0), precision != MEVP_FP64, (size_t)D.ne, c.ns, s));
   if (st == MEVP_OK) st = begin_step_on(&c, s);
   if (st == MEVP_OK) st = subcycles_on(&c, n_subcycles, s);
   if (st == MEVP_OK) st = hip_status(launch_deinterleave2(v_buf(&c, c.cur), v_xy, (size_t)D.nn, s));
-  if (st == MEVP_OK) {
-    if (precision == MEVP_FP64)
-      st = copy(S, S_buf(&c, c.cur), sizeof(double) * nS, s);
-    else
-      st = hip_status(launch_convert_f2d(static_cast<const float *>(S_buf(&c, c.cur)), S, nS, s));
-  }
+  if (st == MEVP_OK)
+    st = hip_status(launch_stress_out(S_buf(&c, c.cur), precision != MEVP_FP64, S, (size_t)D.ne, c.ns, s));
   return st;
 }
 

@@ -439,15 +439,84 @@ __device__ __forceinline__ void relax(const KParams &p, SOld sold, T (&R11)[NS],
   }
 }
 
+// The stress inside the library is [3][ne][NS]: a component's NS coefficients
+// of one element are contiguous (the public layout [3][NS][ne] is converted
+// at set_state / get_state), so an element's row moves as 16-byte vectors
+// when its size allows (FP64 at n_s = 6, 8; float at n_s = 8), else as
+// 8-byte ones (float at n_s = 6) or words.
+template <int NS, class TS>
+struct StressRow {
+  static constexpr int kBytes = NS * (int)sizeof(TS);
+  static constexpr int kVec = kBytes % 16 == 0 ? 16 : kBytes % 8 == 0 ? 8 : (int)sizeof(TS);
+  static constexpr int kPer = kVec / (int)sizeof(TS);  // coefficients per access
+  template <class T>
+  __device__ __forceinline__ static void load(const TS *p, T (&r)[NS]) {
+    if constexpr (kPer == 1) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) r[k] = T(p[k]);
+    } else if constexpr (sizeof(TS) == 8) {
+      const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+      for (int i = 0; i < NS / 2; ++i) {
+        const double2 v = q[i];
+        r[2 * i] = T(v.x);
+        r[2 * i + 1] = T(v.y);
+      }
+    } else if constexpr (kPer == 4) {
+      const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+      for (int i = 0; i < NS / 4; ++i) {
+        const float4 v = q[i];
+        r[4 * i] = T(v.x);
+        r[4 * i + 1] = T(v.y);
+        r[4 * i + 2] = T(v.z);
+        r[4 * i + 3] = T(v.w);
+      }
+    } else {
+      const float2 *q = reinterpret_cast<const float2 *>(p);
+#pragma unroll
+      for (int i = 0; i < NS / 2; ++i) {
+        const float2 v = q[i];
+        r[2 * i] = T(v.x);
+        r[2 * i + 1] = T(v.y);
+      }
+    }
+  }
+  template <class T>
+  __device__ __forceinline__ static void store(TS *p, const T (&r)[NS]) {
+    if constexpr (kPer == 1) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) p[k] = TS(r[k]);
+    } else if constexpr (sizeof(TS) == 8) {
+      double2 *q = reinterpret_cast<double2 *>(p);
+#pragma unroll
+      for (int i = 0; i < NS / 2; ++i) q[i] = double2{double(r[2 * i]), double(r[2 * i + 1])};
+    } else if constexpr (kPer == 4) {
+      float4 *q = reinterpret_cast<float4 *>(p);
+#pragma unroll
+      for (int i = 0; i < NS / 4; ++i)
+        q[i] = float4{TS(r[4 * i]), TS(r[4 * i + 1]), TS(r[4 * i + 2]), TS(r[4 * i + 3])};
+    } else {
+      float2 *q = reinterpret_cast<float2 *>(p);
+#pragma unroll
+      for (int i = 0; i < NS / 2; ++i) q[i] = float2{TS(r[2 * i]), TS(r[2 * i + 1])};
+    }
+  }
+};
+
 template <int NS, class T, class TS>
 __device__ __forceinline__ void store_stress(TS *S_out, size_t ne, int el, const T (&R11)[NS],
                                              const T (&R12)[NS], const T (&R22)[NS]) {
+  StressRow<NS, TS>::store(S_out + (0 * ne + (size_t)el) * NS, R11);
+  StressRow<NS, TS>::store(S_out + (1 * ne + (size_t)el) * NS, R12);
+  StressRow<NS, TS>::store(S_out + (2 * ne + (size_t)el) * NS, R22);
+}
+
+// the stress of element el before the update, as stored
+template <int NS, class TS>
+__device__ __forceinline__ void load_stress(const TS *S_in, size_t ne, int el, TS (&r)[3][NS]) {
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    S_out[(0 * NS + k) * ne + el] = TS(R11[k]);
-    S_out[(1 * NS + k) * ne + el] = TS(R12[k]);
-    S_out[(2 * NS + k) * ne + el] = TS(R22[k]);
-  }
+  for (int c = 0; c < 3; ++c) StressRow<NS, TS>::load(S_in + (c * ne + (size_t)el) * NS, r[c]);
 }
 
 // Per-domain base pointers of the buffers a subcycle reads and writes.
@@ -931,7 +1000,9 @@ __device__ __forceinline__ void element_update(const DevArrays &d, const DomDev 
   load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
   const Ice<NA> ice = load_ice<NA>(d, D, p, el);
   const size_t ne = (size_t)D.ne;
-  auto sold = [&](int c, int k) { return T(S_in[(c * NS + k) * ne + el]); };
+  TS so[3][NS];
+  load_stress<NS, TS>(S_in, ne, el, so);
+  auto sold = [&](int c, int k) { return T(so[c][k]); };
   element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
 }
 
@@ -1252,7 +1323,9 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
         g = load_geo<T, GK>(d, D, ex, ey);
         ice = load_ice<NA>(d, D, p, el);
         load_velocity<T>(D, B.v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
-        auto sold = [&](int c, int k) { return T(B.S_in[(c * NS + k) * ne + el]); };
+        TS so[3][NS];
+        load_stress<NS, TS>(B.S_in, ne, el, so);
+        auto sold = [&](int c, int k) { return T(so[c][k]); };
         if constexpr (GK == kGeoBilinear) {
           factor_mass<NS, T, MP>(BilinearJ<T>(g.map), lmass);
           element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy,

@@ -86,7 +86,7 @@ struct DevArrays {
   const double *ocean;
   double *v;           // [dom][nn][2], interleaved per node (two buffers: v and v + 2 * total nodes)
   double *nc;          // [dom][nn][6] node constants of the velocity update, per node
-  void *S;             // [dom][3][n_s][ne], double or float (two buffers)
+  void *S;             // [dom][3][ne][n_s], double or float (two buffers)
   void *fe;            // [dom][18][ne] element nodal forces, double or float
   int *flag;           // check results
 };
@@ -167,6 +167,12 @@ hipError_t fused_bf16(const DevArrays &, const KParams &, int n_s, int n_a, cons
 // velocities between the public layout [2][n] and the kernels' [n][2]
 hipError_t launch_interleave2(const double *src, double *dst, size_t n, hipStream_t s);
 hipError_t launch_deinterleave2(const double *src, double *dst, size_t n, hipStream_t s);
+// the stress of one domain between the public layout [3][ns][ne] (double)
+// and the kernels' [3][ne][ns] (double, or float when fp32)
+hipError_t launch_stress_in(const double *src, void *dst, bool fp32, size_t ne, int ns,
+                            hipStream_t s);
+hipError_t launch_stress_out(const void *src, bool fp32, double *dst, size_t ne, int ns,
+                             hipStream_t s);
 hipError_t launch_convert_d2f(const double *src, float *dst, size_t n, hipStream_t s);
 hipError_t launch_convert_f2d(const float *src, double *dst, size_t n, hipStream_t s);
 hipError_t launch_check_finite(const double *p, size_t n, int *flag, int bit, hipStream_t s);

@@ -32,6 +32,26 @@ __global__ void k_deinterleave2(const double *src, double *dst, size_t n) {
     dst[n + i] = u.y;
   }
 }
+// the stress between the public layout [3][ns][ne] (double) and the kernels'
+// [3][ne][ns] (double or float)
+template <class TD>
+__global__ void k_stress_in(const double *src, TD *dst, size_t ne, int ns) {
+  const size_t n = 3 * (size_t)ns * ne;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t k = i % ns, e = (i / ns) % ne, c = i / (ns * ne);
+    dst[i] = TD(src[(c * ns + k) * ne + e]);
+  }
+}
+template <class TS>
+__global__ void k_stress_out(const TS *src, double *dst, size_t ne, int ns) {
+  const size_t n = 3 * (size_t)ns * ne;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t k = i % ns, e = (i / ns) % ne, c = i / (ns * ne);
+    dst[(c * ns + k) * ne + e] = double(src[i]);
+  }
+}
 __global__ void k_f2d(const float *src, double *dst, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -207,6 +227,30 @@ hipError_t launch_interleave2(const double *src, double *dst, size_t n, hipStrea
 hipError_t launch_deinterleave2(const double *src, double *dst, size_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_deinterleave2, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_stress_in(const double *src, void *dst, bool fp32, size_t ne, int ns,
+                            hipStream_t s) {
+  const size_t n = 3 * (size_t)ns * ne;
+  if (n == 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL((k_stress_in<float>), dim3(grid_for(n, 256)), dim3(256), 0, s, src,
+                       static_cast<float *>(dst), ne, ns);
+  else
+    hipLaunchKernelGGL((k_stress_in<double>), dim3(grid_for(n, 256)), dim3(256), 0, s, src,
+                       static_cast<double *>(dst), ne, ns);
+  return hipGetLastError();
+}
+hipError_t launch_stress_out(const void *src, bool fp32, double *dst, size_t ne, int ns,
+                             hipStream_t s) {
+  const size_t n = 3 * (size_t)ns * ne;
+  if (n == 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL((k_stress_out<float>), dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       static_cast<const float *>(src), dst, ne, ns);
+  else
+    hipLaunchKernelGGL((k_stress_out<double>), dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       static_cast<const double *>(src), dst, ne, ns);
   return hipGetLastError();
 }
 hipError_t launch_convert_d2f(const double *src, float *dst, size_t n, hipStream_t s) {
