@@ -504,12 +504,24 @@ struct StressRow {
   }
 };
 
-template <int NS, class T, class TS>
+// the new stress of element el; vectors for parallelogram cells (kVec), word
+// by word for general cells, whose larger update has no registers to spare
+template <int NS, class T, class TS, bool kVec = true>
 __device__ __forceinline__ void store_stress(TS *S_out, size_t ne, int el, const T (&R11)[NS],
                                              const T (&R12)[NS], const T (&R22)[NS]) {
-  StressRow<NS, TS>::store(S_out + (0 * ne + (size_t)el) * NS, R11);
-  StressRow<NS, TS>::store(S_out + (1 * ne + (size_t)el) * NS, R12);
-  StressRow<NS, TS>::store(S_out + (2 * ne + (size_t)el) * NS, R22);
+  if constexpr (kVec) {
+    StressRow<NS, TS>::store(S_out + (0 * ne + (size_t)el) * NS, R11);
+    StressRow<NS, TS>::store(S_out + (1 * ne + (size_t)el) * NS, R12);
+    StressRow<NS, TS>::store(S_out + (2 * ne + (size_t)el) * NS, R22);
+  } else {
+    TS *row = S_out + (size_t)el * NS;  // the lane's part; components ne * NS apart
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      row[k] = TS(R11[k]);
+      row[ne * NS + k] = TS(R12[k]);
+      row[2 * ne * NS + k] = TS(R22[k]);
+    }
+  }
 }
 
 // the stress of element el before the update, as stored
@@ -1000,10 +1012,19 @@ __device__ __forceinline__ void element_update(const DevArrays &d, const DomDev 
   load_velocity<T>(D, v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
   const Ice<NA> ice = load_ice<NA>(d, D, p, el);
   const size_t ne = (size_t)D.ne;
-  TS so[3][NS];
-  load_stress<NS, TS>(S_in, ne, el, so);
-  auto sold = [&](int c, int k) { return T(so[c][k]); };
-  element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
+  if constexpr (GK == kGeoAffine) {
+    // parallelogram cells: the old stress as vectors, up front
+    TS so[3][NS];
+    load_stress<NS, TS>(S_in, ne, el, so);
+    auto sold = [&](int c, int k) { return T(so[c][k]); };
+    element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
+  } else {
+    // general cells: coefficient by coefficient, where the relaxation needs
+    // it (held across their larger update, the row costs an occupancy step)
+    const TS *row = S_in + (size_t)el * NS;  // the lane's part; components ne * NS apart
+    auto sold = [&](int c, int k) { return T(row[(size_t)c * ne * NS + k]); };
+    element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
+  }
 }
 
 // Velocity update of one interior node:
@@ -1062,7 +1083,7 @@ __global__ void __launch_bounds__(kElemBlock) k_element(DevArrays d, KParams p, 
   const DomBufs<TS> B(b, D, NS);
   T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
   element_update<NS, NA, T, TS, GK>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22, fx, fy);
-  store_stress<NS, T, TS>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
+  store_stress<NS, T, TS, GK == kGeoAffine>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
   const size_t ne = (size_t)D.ne;
   TS *fe = static_cast<TS *>(d.fe) + (size_t)18 * D.elem_off;
 #pragma unroll
@@ -1235,7 +1256,7 @@ __device__ __forceinline__ void fused_tile(const DevArrays &d, const KParams &p,
       T R11[NS], R12[NS], R22[NS], fx[9], fy[9];
       element_update<NS, NA, T, TS, GK, MP>(d, D, p, B.v_in, B.S_in, el, ex, ey, R11, R12, R22,
                                             fx, fy);
-      if (lx > 0 && ly > 0) store_stress<NS, T, TS>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
+      if (lx > 0 && ly > 0) store_stress<NS, T, TS, GK == kGeoAffine>(B.S_out, (size_t)D.ne, el, R11, R12, R22);
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
         fl[a][tid] = fx[a];
@@ -1323,14 +1344,18 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
         g = load_geo<T, GK>(d, D, ex, ey);
         ice = load_ice<NA>(d, D, p, el);
         load_velocity<T>(D, B.v_in - 2 * (size_t)D.node_off, ex, ey, vx, vy);
-        TS so[3][NS];
-        load_stress<NS, TS>(B.S_in, ne, el, so);
-        auto sold = [&](int c, int k) { return T(so[c][k]); };
         if constexpr (GK == kGeoBilinear) {
+          // general cells: the old stress coefficient by coefficient (see
+          // element_update)
+          const TS *row = B.S_in + (size_t)el * NS;
+          auto sold = [&](int c, int k) { return T(row[(size_t)c * ne * NS + k]); };
           factor_mass<NS, T, MP>(BilinearJ<T>(g.map), lmass);
           element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy,
                                              &lmass);
         } else {
+          TS so[3][NS];
+          load_stress<NS, TS>(B.S_in, ne, el, so);
+          auto sold = [&](int c, int k) { return T(so[c][k]); };
           element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
         }
       } else {
@@ -1343,7 +1368,7 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
           element_compute<NS, NA, T, GK, MP>(p, g, ice, vx, vy, sold, R11, R12, R22, fx, fy);
       }
       if (i == K - 1) {
-        if (lx >= K && ly >= K) store_stress<NS, T, TS>(B.S_out, ne, el, R11, R12, R22);
+        if (lx >= K && ly >= K) store_stress<NS, T, TS, GK == kGeoAffine>(B.S_out, ne, el, R11, R12, R22);
       } else {
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
@@ -1415,8 +1440,11 @@ __global__ void __launch_bounds__((EX + 2 * K - 2) * (EY + 2 * K - 2))
 }
 
 // Fused subcycle kernel: one tile per workgroup, one subcycle.
+// (at least two waves per SIMD: the curved-cell FP64 update would otherwise
+// take a few registers past 256 and run one wave per SIMD)
 template <int NS, int NA, class T, class TS, int GK, int EX, int EY, int MP = 0>
-__global__ void __launch_bounds__(EX *EY) k_fused(DevArrays d, KParams p, const Tile *tiles,
+__global__ void __launch_bounds__(EX *EY) __attribute__((amdgpu_waves_per_eu(2)))
+    k_fused(DevArrays d, KParams p, const Tile *tiles,
                                                    Bufs b) {
   __shared__ T fl[18][EX * EY];
   fused_tile<NS, NA, T, TS, GK, EX, EY, MP>(d, p, tiles[blockIdx.x], b, fl);
