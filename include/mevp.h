@@ -23,6 +23,15 @@
  * Streams. A context enqueues all its work on the stream given at creation
  * (NULL = the default stream). Calls on one context are stream-ordered;
  * a context is not thread-safe. Contexts on one device are independent.
+ * Logging. With the environment variable MEVP_LOG=1 (read once per
+ * process) the library writes host-side lines "[mevp] ..." to stderr: each
+ * context created, every autotuning trial with its time and the choice (or
+ * the cache entry used), a step-graph capture that failed (the context then
+ * launches directly), and every create / step / subcycles / begin_step /
+ * advect / tune / check / step_static / set_config call that returns an
+ * error, with its status. MEVP_LOG=2 adds each launch configuration set and
+ * each step graph captured. Unset or 0: nothing is written. Logging changes
+ * no result and no status.
  * Precision. MEVP_FP64 computes everything in IEEE double. MEVP_MIXED stores
  * the DG stress in float and runs the strain, stress and divergence
  * contractions in float, keeping the ice-strength exponential, the Delta

@@ -5,7 +5,9 @@
 // first element/node) maps for batched launches, and enqueues the kernels of
 // mevp_kernels.hip on the context's stream.
 #include <math.h>
+#include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <memory>
@@ -68,6 +70,50 @@ constexpr long long kIndexMax = 0x7fffffffLL;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool finite(double x) { return isfinite(x) != 0; }
+
+// Host-side log on stderr, enabled by the environment variable MEVP_LOG (read
+// once per process): 1 = context creation, autotuning trials and choice,
+// step-graph capture failures and failing calls; 2 = also every launch
+// configuration set and every step graph captured. Logging never changes a
+// result or a status.
+int log_level() {
+  static const int level = [] {
+    const char *e = getenv("MEVP_LOG");
+    return e ? atoi(e) : 0;
+  }();
+  return level;
+}
+
+__attribute__((format(printf, 2, 3))) void mlog(int level, const char *fmt, ...) {
+  if (log_level() < level) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  fprintf(stderr, "[mevp] %s\n", buf);
+}
+
+const char *strategy_name(int s) {
+  switch (s) {
+    case MEVP_STRATEGY_FUSED: return "fused";
+    case MEVP_STRATEGY_TWO_PHASE: return "two_phase";
+    case MEVP_STRATEGY_PERSISTENT: return "persistent";
+    case MEVP_STRATEGY_FUSED_PAIR: return "fused_pair";
+    case MEVP_STRATEGY_FUSED_TRIPLE: return "fused_triple";
+  }
+  return "?";
+}
+
+const char *precision_name(int p) {
+  return p == MEVP_FP64 ? "fp64" : p == MEVP_MIXED ? "mixed" : p == MEVP_MIXED_BF16 ? "mixed_bf16" : "?";
+}
+
+// A call's status, logged when it is not MEVP_OK.
+mevp_status logged(const char *call, mevp_status st) {
+  if (st != MEVP_OK) mlog(1, "%s: %s (status %d)", call, mevp_status_string(st), (int)st);
+  return st;
+}
 
 mevp_status validate_params(const mevp_params *p) {
   if (!p) return MEVP_EINVAL;
@@ -434,10 +480,15 @@ mevp_status mevp_create(const mevp_params *params, mevp_precision precision,
                         const mevp_domain_desc *domains, int n_domains, void *workspace,
                         size_t ws_bytes, void *hip_stream, mevp_ctx **out) {
   if (out) *out = nullptr;
-  return host_guard([&] {
+  const mevp_status st = host_guard([&] {
     return create_impl(params, precision, domains, n_domains, workspace, ws_bytes, hip_stream,
                        out);
   });
+  if (st == MEVP_OK)
+    mlog(1, "create: %d domain(s), %zu elements, %zu nodes, %s, n_s %d, n_a %d, workspace %zu bytes, device %d",
+         n_domains, (*out)->tot_e, (*out)->tot_n, precision_name(precision), (*out)->ns,
+         (*out)->na, ws_bytes, (*out)->device);
+  return logged("mevp_create", st);
 }
 
 mevp_status mevp_set_params(mevp_ctx *ctx, const mevp_params *params) {
@@ -630,8 +681,8 @@ static mevp_status begin_step_on(mevp_ctx *ctx, hipStream_t stream) {
 
 mevp_status mevp_begin_step(mevp_ctx *ctx) {
   if (!ctx) return MEVP_EINVAL;
-  if (!inputs_set(ctx)) return MEVP_ESTATE;
-  return begin_step_on(ctx, ctx->stream);
+  if (!inputs_set(ctx)) return logged("mevp_begin_step", MEVP_ESTATE);
+  return logged("mevp_begin_step", begin_step_on(ctx, ctx->stream));
 }
 
 // Subcycles per launch of the fused strategies: FUSED_PAIR / FUSED_TRIPLE run
@@ -730,13 +781,13 @@ static mevp_status subcycles_on(mevp_ctx *ctx, int n, hipStream_t stream) {
 
 mevp_status mevp_subcycles(mevp_ctx *ctx, int n) {
   if (!ctx || n < 0) return MEVP_EINVAL;
-  if (!inputs_set(ctx)) return MEVP_ESTATE;
-  return subcycles_on(ctx, n, ctx->stream);
+  if (!inputs_set(ctx)) return logged("mevp_subcycles", MEVP_ESTATE);
+  return logged("mevp_subcycles", subcycles_on(ctx, n, ctx->stream));
 }
 
 mevp_status mevp_advect(mevp_ctx *ctx) {
   if (!ctx) return MEVP_EINVAL;
-  if (!inputs_set(ctx)) return MEVP_ESTATE;
+  if (!inputs_set(ctx)) return logged("mevp_advect", MEVP_ESTATE);
   // the element blocks (grouped by geometry kind) cover every element of every domain
   const size_t n = (size_t)ctx->na * ctx->tot_e;
   double *H = const_cast<double *>(ctx->d.H), *A = const_cast<double *>(ctx->d.A);
@@ -749,7 +800,7 @@ mevp_status mevp_advect(mevp_ctx *ctx) {
     e = launch_advect_stage(ctx->d, ctx->na, L, v, H, A, H1, A1, H2, A2, dt, 0.75, 0.25, s);
   if (e == hipSuccess)
     e = launch_advect_stage(ctx->d, ctx->na, L, v, H, A, H2, A2, H, A, dt, 1.0 / 3.0, 2.0 / 3.0, s);
-  return hip_status(e);
+  return logged("mevp_advect", hip_status(e));
 }
 
 mevp_status mevp_get_fields(mevp_ctx *ctx, int dom, double *H, double *A) {
@@ -778,7 +829,16 @@ mevp_status mevp_get_config(mevp_ctx *ctx, mevp_config *out) {
   return MEVP_OK;
 }
 
+static mevp_status set_config_impl(mevp_ctx *ctx, const mevp_config *cfg);
+
 mevp_status mevp_set_config(mevp_ctx *ctx, const mevp_config *cfg) {
+  const mevp_status st = set_config_impl(ctx, cfg);
+  if (st == MEVP_OK)
+    mlog(2, "config: %s, tile %dx%d", strategy_name(cfg->strategy), cfg->tile_nx, cfg->tile_ny);
+  return logged("mevp_set_config", st);
+}
+
+static mevp_status set_config_impl(mevp_ctx *ctx, const mevp_config *cfg) {
   if (!ctx || !cfg) return MEVP_EINVAL;
   if (cfg->strategy != MEVP_STRATEGY_FUSED && cfg->strategy != MEVP_STRATEGY_TWO_PHASE &&
       cfg->strategy != MEVP_STRATEGY_PERSISTENT && cfg->strategy != MEVP_STRATEGY_FUSED_PAIR &&
@@ -848,10 +908,18 @@ static mevp_status capture_step(mevp_ctx *ctx, int n, mevp_ctx::StepGraph &g) {
   g.g = graph;
   g.x = exec;
   g.n = n;
+  mlog(2, "step: graph captured (start of step + %d subcycles, %s, tile %dx%d)", n,
+       strategy_name(ctx->strategy), kTileShapes[ctx->shape][0] - 1, kTileShapes[ctx->shape][1] - 1);
   return MEVP_OK;
 }
 
+static mevp_status step_impl(mevp_ctx *ctx, int n_subcycles);
+
 mevp_status mevp_step(mevp_ctx *ctx, int n_subcycles) {
+  return logged("mevp_step", step_impl(ctx, n_subcycles));
+}
+
+static mevp_status step_impl(mevp_ctx *ctx, int n_subcycles) {
   if (!ctx || n_subcycles < 0) return MEVP_EINVAL;
   if (!inputs_set(ctx)) return MEVP_ESTATE;
   // replay a captured step when nothing needs per-launch events; cooperative
@@ -865,6 +933,7 @@ mevp_status mevp_step(mevp_ctx *ctx, int n_subcycles) {
     }
     if (!g.x && capture_step(ctx, n_subcycles, g) != MEVP_OK) {
       ctx->use_graph = false;  // capture unsupported here: launch eagerly from now on
+      mlog(1, "step: graph capture failed, launching the kernels directly from now on");
     } else if (g.x) {
       if (hipGraphLaunch(g.x, ctx->stream) != hipSuccess) return MEVP_EDEVICE;
       ctx->cur = g.cur_after;
@@ -909,8 +978,8 @@ mevp_status mevp_check_inputs(mevp_ctx *ctx) {
     st = hip_status(launch_check_jacobian(ctx->d, ctx->ns, (int)ctx->eblk_h.size(), 2, s));
   int flag = 0;
   if (st == MEVP_OK) st = read_flag(ctx, &flag);
-  if (st != MEVP_OK) return st;
-  return flag ? MEVP_ENONFINITE : MEVP_OK;
+  if (st != MEVP_OK) return logged("mevp_check_inputs", st);
+  return logged("mevp_check_inputs", flag ? MEVP_ENONFINITE : MEVP_OK);
 }
 
 mevp_status mevp_check_state(mevp_ctx *ctx) {
@@ -927,8 +996,8 @@ mevp_status mevp_check_state(mevp_ctx *ctx) {
   }
   int flag = 0;
   if (st == MEVP_OK) st = read_flag(ctx, &flag);
-  if (st != MEVP_OK) return st;
-  return flag ? MEVP_ENONFINITE : MEVP_OK;
+  if (st != MEVP_OK) return logged("mevp_check_state", st);
+  return logged("mevp_check_state", flag ? MEVP_ENONFINITE : MEVP_OK);
 }
 
 mevp_status mevp_timing_enable(mevp_ctx *ctx, int max_launches) {
@@ -1036,6 +1105,8 @@ static mevp_status tune_impl(mevp_ctx *ctx, int n_trial, const char *cache_path,
   const std::string key = tune_key(ctx);
   mevp_config cfg;
   if (cache_lookup(cache_path, key, &cfg) && mevp_set_config(ctx, &cfg) == MEVP_OK) {
+    mlog(1, "tune: %s from the cache: %s, tile %dx%d", key.c_str(), strategy_name(cfg.strategy),
+         cfg.tile_nx, cfg.tile_ny);
     if (chosen) *chosen = cfg;
     return MEVP_OK;
   }
@@ -1086,8 +1157,15 @@ static mevp_status tune_impl(mevp_ctx *ctx, int n_trial, const char *cache_path,
     if (st == MEVP_OK) st = hip_status(hipEventElapsedTime(&ms, e0, e1));
     // every configuration must reproduce the first one bit for bit
     if (st == MEVP_OK) st = save_state(ctx, i == 0 ? ref : got);
-    if (st == MEVP_OK && i > 0 && (got.size() != ref.size() || memcmp(got.data(), ref.data(), ref.size()) != 0))
+    if (st == MEVP_OK && i > 0 && (got.size() != ref.size() || memcmp(got.data(), ref.data(), ref.size()) != 0)) {
       st = MEVP_EINTERNAL;
+      mlog(1, "tune: %s, tile %dx%d differs from %s, tile %dx%d after %d subcycles",
+           strategy_name(cand[i].strategy), cand[i].tile_nx, cand[i].tile_ny,
+           strategy_name(cand[0].strategy), cand[0].tile_nx, cand[0].tile_ny, n_trial);
+    }
+    if (st == MEVP_OK)
+      mlog(1, "tune: %s, tile %dx%d: %.3f ms for %d subcycles", strategy_name(cand[i].strategy),
+           cand[i].tile_nx, cand[i].tile_ny, ms, n_trial);
     if (st == MEVP_OK && (best_i < 0 || ms < best)) {
       best = ms;
       best_i = (int)i;
@@ -1104,6 +1182,8 @@ static mevp_status tune_impl(mevp_ctx *ctx, int n_trial, const char *cache_path,
   if (rs != MEVP_OK) return rs;
   if (cs != MEVP_OK) return cs;
   if (chosen) *chosen = cand[best_i];
+  mlog(1, "tune: %s: chose %s, tile %dx%d", key.c_str(), strategy_name(cand[best_i].strategy),
+       cand[best_i].tile_nx, cand[best_i].tile_ny);
   if (cache_path) {
     FILE *f = fopen(cache_path, "a");
     if (f) {
@@ -1116,7 +1196,7 @@ static mevp_status tune_impl(mevp_ctx *ctx, int n_trial, const char *cache_path,
 }
 
 mevp_status mevp_tune(mevp_ctx *ctx, int n_trial, const char *cache_path, mevp_config *chosen) {
-  return host_guard([&] { return tune_impl(ctx, n_trial, cache_path, chosen); });
+  return logged("mevp_tune", host_guard([&] { return tune_impl(ctx, n_trial, cache_path, chosen); }));
 }
 
 // ---------------------------------------------------------------------------
@@ -1162,6 +1242,7 @@ mevp_status scratch_base(int dev, char **out) {
     }
     g_scratch_ptr[dev] = ptr;
     g_scratch_status[dev] = MEVP_OK;
+    mlog(1, "step_static: %zu bytes of file-scope scratch on device %d", (size_t)MEVP_STATIC_SCRATCH_BYTES, dev);
   });
   *out = static_cast<char *>(g_scratch_ptr[dev]);
   return g_scratch_status[dev];
@@ -1333,10 +1414,10 @@ mevp_status mevp_step_static(const mevp_params *params, mevp_precision precision
                              const double *H, const double *A, const double *wind_xy,
                              const double *ocean_xy, double *v_xy, double *S, int n_subcycles,
                              void *hip_stream) {
-  return host_guard([&] {
+  return logged("mevp_step_static", host_guard([&] {
     return step_static_impl(params, precision, domain, vertex_xy, H, A, wind_xy, ocean_xy, v_xy,
                             S, n_subcycles, hip_stream);
-  });
+  }));
 }
 
 void mevp_destroy(mevp_ctx *ctx) {

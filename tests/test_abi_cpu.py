@@ -221,3 +221,45 @@ def test_bf16_precision_sizes_and_limits(M):
             M.workspace_size([d], "mixed_bf16")
         assert ei.value.status == -1
     assert _step_static(M, doms=(8, 8, 3, 1), prec=2) == -1
+
+
+_LOG_SCRIPT = r"""
+import ctypes as C, sys
+sys.path.insert(0, sys.argv[1])
+import paper_2402_00466_amd as M
+L = M.lib()
+arr = (M.mevp.CDomain * 1)(M.mevp.CDomain(8, 8, 6, 1))
+p = M.Params().to_c()
+h = C.c_void_p()
+need = M.workspace_size([M.Domain(8, 8, 6, 1)])
+print(L.mevp_create(C.byref(p), 0, arr, 1, None, C.c_size_t(need), None, C.byref(h)))
+print(L.mevp_create(C.byref(p), 0, arr, 1, C.c_void_p(0x10000000), C.c_size_t(need - 1), None,
+                    C.byref(h)))
+print(L.mevp_step(None, 1))
+d = M.mevp.CDomain(8, 8, 6, 1)
+print(L.mevp_step_static(C.byref(p), 0, C.byref(d), *([C.c_void_p(0x10000000)] * 7), -1, None))
+"""
+
+
+@pytest.mark.parametrize("level", [None, "0", "1"])
+def test_log_env_reports_failing_calls_on_stderr(M, level):
+    """MEVP_LOG=1 writes one line per failing call to stderr ("[mevp] call:
+    status string (status n)"); unset or 0 writes nothing. Statuses are the
+    same either way."""
+    import subprocess
+    import sys
+    env = {k: v for k, v in os.environ.items() if k != "MEVP_LOG"}
+    if level is not None:
+        env["MEVP_LOG"] = level
+    r = subprocess.run([sys.executable, "-c", _LOG_SCRIPT, ROOT], capture_output=True, text=True,
+                       env=env, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split() == ["-1", "-2", "-1", "-1"]
+    lines = [x for x in r.stderr.splitlines() if x.startswith("[mevp]")]
+    if level == "1":
+        assert lines == ["[mevp] mevp_create: invalid argument (status -1)",
+                         "[mevp] mevp_create: workspace too small (status -2)",
+                         "[mevp] mevp_step: invalid argument (status -1)",
+                         "[mevp] mevp_step_static: invalid argument (status -1)"]
+    else:
+        assert lines == []

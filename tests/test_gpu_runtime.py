@@ -127,3 +127,55 @@ def test_launch_depth_matches_launches(M, kind):
         assert n_launch == want, (strategy, n_launch, want)
     ctx.sync()
     ctx.close()
+
+
+_LOG_RUN = r"""
+import hashlib, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+torch.cuda.set_device(0)
+import paper_2402_00466_amd as M
+from synth_inputs import make_domain
+d = make_domain(40, 30, 6, 1, seed=13, h=2e3)
+ctx = M.Context([M.Domain(d.nx, d.ny, d.n_s, d.n_a)])
+ctx.upload(0, d)
+ctx.tune(n_trial=3)
+ctx.step(10)
+v, S = ctx.get_state(0)
+ctx.sync()
+print(hashlib.sha256(v.cpu().numpy().tobytes() + S.cpu().numpy().tobytes()).hexdigest())
+"""
+
+
+def test_log_env_traces_create_tune_and_capture(M):
+    """MEVP_LOG=2 writes the context, every tuner trial and the choice, the
+    configurations set and the captured step graph to stderr; the state after a
+    tuned step is the same with logging off (in a process of its own each, as
+    the variable is read once per process)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    runs = []
+    for level in (None, "2"):
+        env = {k: v for k, v in os.environ.items() if k != "MEVP_LOG"}
+        if level:
+            env["MEVP_LOG"] = level
+        log(f"child process, MEVP_LOG={level}")
+        r = subprocess.run([sys.executable, "-c", _LOG_RUN, root], capture_output=True,
+                           text=True, env=env, timeout=240)
+        assert r.returncode == 0, r.stderr[-3000:]
+        runs.append(r)
+    assert runs[0].stdout == runs[1].stdout
+    assert "[mevp]" not in runs[0].stderr
+    lines = [x for x in runs[1].stderr.splitlines() if x.startswith("[mevp]")]
+    assert lines[0].startswith("[mevp] create: 1 domain(s), 1200 elements, "), lines[:3]
+    assert "fp64, n_s 6, n_a 1" in lines[0]
+    trials = [x for x in lines if x.startswith("[mevp] tune: ") and x.endswith(" ms for 3 subcycles")]
+    assert len(trials) == 3 * len(M.TILES) + 1, trials   # fused, pair, triple per tile; two-phase
+    chose = [x for x in lines if " chose " in x]
+    assert len(chose) == 1 and chose[0].startswith("[mevp] tune: gfx950/fp64/ns6/na1/dom1/el1200/")
+    assert any(x.startswith("[mevp] config: ") for x in lines)
+    assert any(x.startswith("[mevp] step: graph captured (start of step + 10 subcycles, ")
+               for x in lines)
+    assert not any("status" in x for x in lines), lines
