@@ -488,6 +488,9 @@ def main():
                 "roofline_frac": r["roofline"]["frac"],
                 "achieved_GBs": r["roofline"]["achieved"],
                 "advection_frac": r["advection"]["frac"]}
+            if r["roofline"].get("measured_GBs"):
+                variants[key]["measured_GBs"] = r["roofline"]["measured_GBs"]
+                variants[key]["measured_frac"] = r["roofline"]["measured_frac"]
             log(f"  {r['value']:.3e} element-subcycles/s ({r['config']['strategy']} "
                 f"{r['config']['tile']}), {r['roofline']['frac']:.3f} of HBM peak")
             del ds
