@@ -1122,10 +1122,10 @@ static mevp_status tune_impl(mevp_ctx *ctx, int n_trial, const char *cache_path,
   }
   if (ctx->prec != MEVP_MIXED_BF16)
     cand.push_back(mevp_config{MEVP_STRATEGY_TWO_PHASE, kTileShapes[0][0] - 1, kTileShapes[0][1] - 1});
-  // PERSISTENT is not a candidate: its grid-wide barrier between subcycles
-  // costs several microseconds on MI355X, while consecutive launches of a
-  // replayed graph are a fraction of a microsecond apart, so it never wins
-  // (it stays available through mevp_set_config).
+  // PERSISTENT is not a candidate: on MI355X its grid-wide barrier and static
+  // tile assignment cost about 30 us per subcycle over graph-replayed launches
+  // of the same tiles, which start a fraction of a microsecond apart, so it
+  // never wins (it stays available through mevp_set_config).
 
   mevp_config before;
   mevp_get_config(ctx, &before);
