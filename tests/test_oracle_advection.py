@@ -149,3 +149,38 @@ def test_rate_matches_exact_assembly(oracle_mod, na):
                       np.array([[float(z) for z in r] for r in U]))
     ref = np.array([[float(z) for z in r] for r in exact])
     assert np.abs(L - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def _sheared_vertices(nx, ny, h, sx, sy):
+    """Parallelogram cells with edge vectors (h, sy h) and (sx h, h): both
+    off-diagonal Jacobian entries are non-zero."""
+    iy, ix = np.meshgrid(np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    return np.stack([(ix + sx * iy).ravel() * h, (iy + sy * ix).ravel() * h]).astype(np.float64)
+
+
+@pytest.mark.parametrize("na", [3, 6])
+@pytest.mark.parametrize("cells", ["sheared", "bilinear"])
+def test_free_stream_rate_is_zero_on_general_cells(oracle_mod, na, cells):
+    """A constant field carried by a constant velocity has a zero rate in every
+    cell: the volume term integrates U v.grad(psi_k) exactly (a polynomial of
+    low degree after the Jacobian's adjugate) and equals the sum of the edge
+    fluxes, each edge's upwind value being the same constant (own trace on the
+    domain boundary). The cells have both off-diagonal Jacobian entries
+    non-zero, so every term of grad psi = J^-T (dpsi/dxi, dpsi/deta) enters."""
+    nx, ny, h = 6, 5, 1000.0
+    if cells == "sheared":
+        V = _sheared_vertices(nx, ny, h, 0.3, 0.2)
+    else:
+        V = perturbed_vertices(nx, ny, h, amp=0.2, seed=5)
+    m = oracle_mod.Mesh(nx, ny, 6, na, V)
+    U = np.zeros((na, m.ne))
+    U[0] = 0.9
+    ux, uy = 0.4, -0.25
+    v = np.stack([np.full(m.nn, ux), np.full(m.nn, uy)])
+    L = m.advect_rate(v, U)
+    scale = 0.9 * np.hypot(ux, uy) / h
+    assert np.abs(L).max() <= 1e-12 * scale
+    # a non-constant field does move (the test is not vacuous)
+    U2 = U.copy()
+    U2[1] = 0.2
+    assert np.abs(m.advect_rate(v, U2)).max() > 1e-3 * scale

@@ -221,3 +221,52 @@ def test_first_subcycle_from_rest_follows_the_pressure_gradient(oracle_mod):
     assert np.abs(vx - vx_expect).max() < 1e-12 * scale
     assert np.abs(vy).max() < 1e-12 * scale
     np.testing.assert_allclose(S[0, 0], -p.Pstar * H[0] / (2 * p.alpha), rtol=1e-13)
+
+
+def test_ice_free_interior_nodes_are_held_at_rest(oracle_mod):
+    """At an interior node with no ice (M^H = m^A = 0) the lumped balance has
+    no mass on either side and no drag: the velocity update holds the node at
+    rest in both components, whatever v^(p-1), v^n and the nodal force (the
+    library's reading of the degenerate node); every other interior node still
+    satisfies the balance."""
+    O = oracle_mod
+    p = O.Params(f_cor=1.46e-4, beta=50.0)
+    d = make_domain(5, 4, 6, 1, seed=43, h=3000.0, perturb=0.1)
+    m = O.Mesh(d.nx, d.ny, 6, 1, d.vertices)
+    rng = np.random.default_rng(44)
+    MH, mA = m.node_masses(p, d.H, d.A)
+    inner = interior_mask(d.nx, d.ny)
+    free = np.flatnonzero(inner)[[0, 7, 20, 33]]
+    MH[free] = 0.0
+    mA[free] = 0.0
+    tau = m.air_stress(p, d.wind)
+    vprev = rng.normal(0, 0.05, (2, m.nn))
+    vn = rng.normal(0, 0.05, (2, m.nn))
+    ocean = rng.normal(0, 0.1, (2, m.nn))
+    F = rng.normal(0, 1.0, (2, m.nn)) * np.abs(MH / p.dt * vn).max()
+    v = m.velocity(p, F, MH, mA, tau, ocean, vn, vprev)
+    assert (v[:, free] == 0).all()
+    assert (v[:, ~inner] == 0).all()
+    rest = inner.copy()
+    rest[free] = False
+    drag = p.rho_o * p.C_o * np.hypot(ocean[0] - vprev[0], ocean[1] - vprev[1])
+    kxv = np.stack([-v[1], v[0]])
+    res = (MH / p.dt * (p.beta * (v - vprev) + v - vn) - F - mA * tau
+           - mA * drag * (ocean - v) + p.f_cor * MH * kxv)
+    terms = np.abs(F) + np.abs(MH / p.dt * (p.beta + 1) * v) + np.abs(mA * tau)
+    assert (np.abs(res[:, rest]) <= 1e-13 * terms[:, rest].max()).all()
+
+
+def test_zero_subcycles_leave_the_state_unchanged(oracle_mod):
+    """n_sub = 0 is a valid call that changes nothing; n_sub < 0 is rejected."""
+    O = oracle_mod
+    p = O.Params()
+    d = make_domain(4, 3, 6, 1, seed=45, h=2000.0)
+    m = O.Mesh(d.nx, d.ny, 6, 1, d.vertices)
+    v0, S0 = random_state(d.nx, d.ny, 6, seed=46)
+    v, S = m.subcycles(p, d.H, d.A, d.wind, d.ocean, v0, v0, S0, 0)
+    assert np.array_equal(v, v0) and np.array_equal(S, S0)
+    v, S = m.step(p, d.H, d.A, d.wind, d.ocean, v0, S0, 0)
+    assert np.array_equal(v, v0) and np.array_equal(S, S0)
+    with pytest.raises(RuntimeError):
+        m.subcycles(p, d.H, d.A, d.wind, d.ocean, v0, v0, S0, -1)

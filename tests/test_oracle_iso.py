@@ -236,3 +236,33 @@ def test_iso_geometry_is_translation_invariant(oracle_mod):
     for e in (0, 13, 29):
         for a, b in zip(m1.element_geometry(e), m0.element_geometry(e)):
             assert rel(a, b) < 1e-14
+
+
+@pytest.mark.parametrize("ns", [3, 6])
+@pytest.mark.parametrize("kind", ["bilinear", "curved"])
+def test_basis_gradients_reproduce_the_coordinates(oracle_mod, ns, kind):
+    """The coordinate functions lie in each cell's CG2 space (the bilinear map
+    is biquadratic-representable, the isoparametric map is one by definition),
+    so at every Gauss point of every element the gradient tables give
+    sum_a grad phi_a = 0, sum_a x_a grad phi_a = (1, 0) and
+    sum_a y_a grad phi_a = (0, 1), with x_a, y_a the element's nine node
+    positions (local node a = 3 b + c at row 2 ey + b, column 2 ex + c)."""
+    nx, ny = 5, 4
+    if kind == "bilinear":
+        V = perturbed_vertices(nx, ny, 2000.0, amp=0.2, seed=9)
+        m = oracle_mod.Mesh(nx, ny, ns, 1, V)
+        nodes = bilinear_nodes(V, nx, ny)
+    else:
+        m, nodes = curved_mesh(oracle_mod, nx, ny, ns, 1)
+    NX = 2 * nx + 1
+    for e in range(m.ne):
+        ex, ey = e % nx, e // nx
+        idx = [(2 * ey + a // 3) * NX + 2 * ex + a % 3 for a in range(9)]
+        xa, ya = nodes[0][idx], nodes[1][idx]
+        wd, gx, gy = m.element_geometry(e)
+        assert gx.shape == (9, m.ng) and (wd > 0).all()
+        h = 2000.0
+        for G, want in ((gx, (1.0, 0.0)), (gy, (0.0, 1.0))):
+            assert np.abs(G.sum(axis=0)).max() < 1e-12 / h
+            assert np.abs(xa @ G - want[0]).max() < 1e-12
+            assert np.abs(ya @ G - want[1]).max() < 1e-12

@@ -118,6 +118,23 @@ MUTANTS = {
                                "R[k] -= gw[1] * vn * Uup * dg_basis(k, xi, eta);")],
     "advection basis derivative": [("case 4: *dxi = t; *deta = s; return;",
                                     "case 4: *dxi = s; *deta = t; return;")],
+    "advection gradient x row J10 sign": [("double gx = (J11 * dxi - J10 * deta) / det;",
+                                           "double gx = (J11 * dxi + J10 * deta) / det;")],
+    "advection gradient y row J01 sign": [("double gy = (-J01 * dxi + J00 * deta) / det;",
+                                           "double gy = (J01 * dxi + J00 * deta) / det;")],
+    "reference xi-gradient table with xi and eta swapped": [
+        ("if (dxi) dxi[a * ng + q] = dlag2(c, xi) * lag2(b, eta);",
+         "if (dxi) dxi[a * ng + q] = dlag2(c, eta) * lag2(b, xi);")],
+    "reference eta-gradient table differentiates in xi": [
+        ("if (deta) deta[a * ng + q] = lag2(c, xi) * dlag2(b, eta);",
+         "if (deta) deta[a * ng + q] = dlag2(c, xi) * lag2(b, eta);")],
+    # degenerate and edge cases, accessors
+    "ice-free node keeps its y velocity": [("      v[nn + j] = 0.0;\n    } else {", "    } else {")],
+    "zero subcycles rejected": [("if (!m || !p || n_sub < 0) return -1;",
+                                 "if (!m || !p || n_sub <= 0) return -1;")],
+    "geometry accessor copies part of the y gradients": [
+        ("memcpy(dphiy, m->dphiy + (size_t)e * 9 * ng, sizeof(double) * 9 * ng);",
+         "memcpy(dphiy, m->dphiy + (size_t)e * 9 * ng, sizeof(double) * 8 * ng);")],
 }
 
 

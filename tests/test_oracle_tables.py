@@ -88,3 +88,23 @@ def test_listing_constants_golden(oracle_mod):
     np.testing.assert_allclose(s[0, :, 0], PD * (gold["s11"]["e11"] * e[0] + gold["s11"]["e22"] * e[2]) + gold["s11"]["P"] * Pg, rtol=1e-13)
     np.testing.assert_allclose(s[1, :, 0], PD * gold["s12"]["e12"] * e[1], rtol=1e-13)
     np.testing.assert_allclose(s[2, :, 0], PD * (gold["s22"]["e22"] * e[2] + gold["s22"]["e11"] * e[0]) + gold["s22"]["P"] * Pg, rtol=1e-13)
+
+
+@pytest.mark.parametrize("ns", [3, 6])
+def test_q2_gradients_differentiate_the_q2_space_exactly(oracle_mod, ns):
+    """The reference gradient tables differentiate every function of the Q2
+    space exactly: for f = xi^i eta^j (i, j <= 2), sum_a f(node_a) dphi_a/dxi
+    at each Gauss point is df/dxi there, likewise for eta (node a = 3 b + c at
+    (c/2, b/2))."""
+    gp, gw, psiS, psiA, phi, dxi, deta = oracle_mod.tables(ns)
+    ngp = len(gp)
+    xq, eq = np.tile(gp, ngp), np.repeat(gp, ngp)
+    xa = np.array([(a % 3) / 2 for a in range(9)])
+    ea = np.array([(a // 3) / 2 for a in range(9)])
+    for i in range(3):
+        for j in range(3):
+            f = xa ** i * ea ** j
+            dfx = i * xq ** max(i - 1, 0) * eq ** j
+            dfe = j * xq ** i * eq ** max(j - 1, 0)
+            np.testing.assert_allclose(f @ dxi, dfx, atol=1e-14)
+            np.testing.assert_allclose(f @ deta, dfe, atol=1e-14)
