@@ -82,7 +82,12 @@ typedef enum {
 typedef enum {
   MEVP_FP64 = 0,
   MEVP_MIXED = 1,
-  MEVP_MIXED_BF16 = 2
+  MEVP_MIXED_BF16 = 2,
+  /* not precisions: they give the enum the range of int, so that any int a
+   * caller passes is a value of the type and the library rejects it (EINVAL)
+   * instead of reading an out-of-range enum */
+  MEVP_PRECISION_RANGE_MIN_ = -2147483647 - 1,
+  MEVP_PRECISION_RANGE_MAX_ = 2147483647
 } mevp_precision;
 
 /* Physical and iteration parameters (mevp_default_params fills the values
@@ -141,7 +146,10 @@ typedef enum {
   MEVP_STRATEGY_TWO_PHASE = 1,
   MEVP_STRATEGY_PERSISTENT = 2,
   MEVP_STRATEGY_FUSED_PAIR = 3,
-  MEVP_STRATEGY_FUSED_TRIPLE = 4
+  MEVP_STRATEGY_FUSED_TRIPLE = 4,
+  /* not strategies: the range of int, as for mevp_precision */
+  MEVP_STRATEGY_RANGE_MIN_ = -2147483647 - 1,
+  MEVP_STRATEGY_RANGE_MAX_ = 2147483647
 } mevp_strategy;
 
 /* Launch configuration: strategy and the fused kernels' tile of owned
