@@ -106,3 +106,33 @@ def test_advection_bytes_per_step():
     u = 8 * 6 * 2 * 3 * 8
     per_stage_v_geo = 17 * 13 * 16 + 9 * 7 * 16
     assert bench.advect_bytes([d]) == (u + u) + 2 * (2 * u + u) + 3 * per_stage_v_geo
+
+
+@pytest.mark.parametrize("ws,bound", [(5 << 30, "hbm"), (64 << 20, "latency/issue (cache-resident)")])
+def test_roofline_fields_with_and_without_a_traffic_record(monkeypatch, ws, bound):
+    """The roofline object: `achieved` is the algorithmic bytes per launch over
+    the launch time; a traffic record for the current sources adds the measured
+    HBM rate and fraction over the same time; a working set that fits the
+    Infinity Cache is labelled cache-resident; the FP64 rate is reported for
+    the single-domain DG2 FP64 workloads only."""
+    import bench
+    from synth_inputs import make_domain
+    d = make_domain(8, 8, 6, 1, seed=1)
+    monkeypatch.setattr(bench, "working_set_bytes", lambda *a: ws)
+    kbytes, kms = 3.0e9, 0.5
+    for traffic in (1.5e9, None):
+        monkeypatch.setattr(bench, "load_traffic", lambda *a, t=traffic: t)
+        r = bench.roofline([d], "fp64", "8x8-dg2", "fused_triple", (16, 16), "k", kbytes, kms, 3)
+        assert r["bound"] == bound and r["unit"] == "GB/s" and r["peak"] == bench.HBM_PEAK_GBS
+        assert r["achieved"] == pytest.approx(kbytes / 0.5e-3 / 1e9)
+        assert r["frac"] == pytest.approx(r["achieved"] / bench.HBM_PEAK_GBS)
+        assert r["traffic"] == traffic
+        if traffic:
+            assert r["measured_GBs"] == pytest.approx(traffic / 0.5e-3 / 1e9)
+            assert r["measured_frac"] == pytest.approx(r["measured_GBs"] / bench.HBM_PEAK_GBS)
+        else:
+            assert "measured_GBs" not in r and "measured_frac" not in r
+        assert r["fp64_TFs"] == pytest.approx(
+            bench.FP64_FLOP_PER_ELEMENT_SUBCYCLE * 64 * 3 / 0.5e-3 / 1e12)
+    r = bench.roofline([d], "mixed", "8x8-dg2", "fused_triple", (16, 16), "k", kbytes, kms, 3)
+    assert "fp64_TFs" not in r
