@@ -15,8 +15,10 @@
  * ---------------------------------------
  * Pointers. Every array argument is a caller-owned DEVICE pointer (host
  * pointers are accepted by the copy-in/out calls, which then block the
- * host). The library never allocates device memory: all of its state lives
- * in the workspace the caller passes to mevp_create.
+ * host). The library never calls a device allocator: a context's state lives
+ * in the workspace the caller passes to mevp_create, and mevp_step_static
+ * works in a file-scope device array (MEVP_STATIC_SCRATCH_BYTES per GPU, part
+ * of the library's code object on that GPU).
  * Errors. Every call returns a mevp_status; no call aborts or throws. All
  * argument validation happens on the host before anything is enqueued.
  * Asynchronous HIP failures surface at the next mevp_sync / mevp_check_*.
