@@ -184,3 +184,21 @@ def test_free_stream_rate_is_zero_on_general_cells(oracle_mod, na, cells):
     U2 = U.copy()
     U2[1] = 0.2
     assert np.abs(m.advect_rate(v, U2)).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize("na", [1, 3])
+def test_both_fields_advected_alike(oracle_mod, na):
+    """H and A go through the same scheme, each on its own: swapping them at
+    the input swaps the outputs bit for bit, both move under a non-zero
+    velocity, and both keep their cell integrals."""
+    d = make_domain(7, 6, 6, na, seed=7, h=2e3, perturb=0.1, ho_amp=0.2)
+    m = oracle_mod.Mesh(7, 6, 6, na, d.vertices)
+    rng = np.random.default_rng(8)
+    v = rng.normal(0, 0.3, (2, m.nn)) * _interior_mask(7, 6)
+    H1, A1 = m.advect(600.0, v, d.H, d.A)
+    A2, H2 = m.advect(600.0, v, d.A, d.H)
+    assert np.array_equal(H1, H2) and np.array_equal(A1, A2)
+    for U0, U1 in ((d.H, H1), (d.A, A1)):
+        assert np.abs(U1 - U0).max() > 1e-6 * np.abs(U0).max()
+        m0 = _cell_integrals(m, U0)
+        assert abs(_cell_integrals(m, U1) - m0) < 1e-12 * abs(m0)

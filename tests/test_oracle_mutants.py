@@ -130,6 +130,7 @@ MUTANTS = {
          "if (deta) deta[a * ng + q] = dlag2(c, xi) * lag2(b, eta);")],
     # degenerate and edge cases, accessors
     "ice-free node keeps its y velocity": [("      v[nn + j] = 0.0;\n    } else {", "    } else {")],
+    "concentration not advected": [("  advect_field(m, dt, v, A);\n", "")],
     "zero subcycles rejected": [("if (!m || !p || n_sub < 0) return -1;",
                                  "if (!m || !p || n_sub <= 0) return -1;")],
     "geometry accessor copies part of the y gradients": [
