@@ -263,3 +263,17 @@ def test_log_env_reports_failing_calls_on_stderr(M, level):
                          "[mevp] mevp_step_static: invalid argument (status -1)"]
     else:
         assert lines == []
+
+
+def test_step_static_size_limit_matches_the_header(M):
+    """The array holds about 610 B per element at n_s = 6 in FP64 and 470 B in
+    mixed precision (64 MiB: ~1.1e5 / ~1.4e5 elements): the largest square
+    domains that pass the host's size check are 330^2 and 375^2 (they then
+    need a device), one size up is ENOMEM."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a device is present; the fake pointers must not reach it")
+    assert _step_static(M, doms=(330, 330, 6, 1)) == -3
+    assert _step_static(M, doms=(332, 332, 6, 1)) == -2
+    assert _step_static(M, doms=(375, 375, 6, 1), prec=1) == -3
+    assert _step_static(M, doms=(380, 380, 6, 1), prec=1) == -2
