@@ -256,7 +256,11 @@ mevp_status mevp_set_forcing(mevp_ctx *ctx, int dom, const double *wind_xy,
  * coefficients that the stress update of Listing 1 and the appendix listing
  * reads and relaxes in place (Eq. (si:mevp) carries sigma^(p) from one
  * subcycle to the next; the state also carries S from one step to the next).
- * Stream-ordered copy into the current state buffers. In MEVP_MIXED and
+ * Stream-ordered copy into the current state buffers: the arrays are copied
+ * to the device and reordered there into the library's internal layouts
+ * (velocities interleaved per node, each element's coefficients of one
+ * stress component contiguous), with the context's second state buffer as
+ * staging. In MEVP_MIXED and
  * MEVP_MIXED_BF16, S is rounded to float on the device, so S must be a device pointer there
  * (EINVAL otherwise). EINVAL on a bad domain or a NULL pointer. */
 mevp_status mevp_set_state(mevp_ctx *ctx, int dom, const double *v_xy, const double *S);
@@ -319,8 +323,9 @@ mevp_status mevp_get_fields(mevp_ctx *ctx, int dom, double *H, double *A);
 /* Copy out the state of domain `dom` in the layouts of mevp_set_state: the
  * velocity v and the DG stress S after the last subcycle (Eq. (si:mevp);
  * the in-out stress arguments of the appendix listing). Either pointer may be
- * NULL. Stream-ordered: the values are valid once the stream has passed the
- * call (mevp_sync). In MEVP_MIXED and MEVP_MIXED_BF16, S is widened from
+ * NULL. The state is reordered from the internal layouts on the device (the
+ * second state buffer as staging), then copied out. Stream-ordered: the
+ * values are valid once the stream has passed the call (mevp_sync). In MEVP_MIXED and MEVP_MIXED_BF16, S is widened from
  * float on the device and must be a device pointer (EINVAL otherwise). EINVAL on a bad domain. */
 mevp_status mevp_get_state(mevp_ctx *ctx, int dom, double *v_xy, double *S);
 
